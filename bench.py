@@ -1,0 +1,200 @@
+"""Insertion benchmark on one MI355X.
+
+A step is one insertion pass of the whole hot path (expand, sample, allocate,
+store) over one batch.  The default workload is the aerial-LiDAR-shaped cloud:
+100M points on a 1 km x 1 km fBm heightfield, 1M-point batches cut from
+Morton order and shuffled (seed 1), root cube [0, 1024)^3 m, T = 50,000,
+128^3 grids, Dmax = 16, chunks of 1,000.  The whole cloud is resident in HBM
+before timing starts; W warmup batches go into a scratch build that is then
+reset, and the timed region inserts batches 0..K-1 into an empty octree.
+
+Printed JSON line: points/s over the timed region, ms per step (= per 1M-point
+update), p50/p99 per-update latency from HIP events, the dominant kernel's
+roofline (algorithmic bytes per launch / its event-timed average duration,
+against 8 TB/s HBM) and the CPU oracle (sequential C inserter, one thread)
+timed on a bounded prefix of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "aerial": dict(
+        desc="aerial-LiDAR-shaped heightfield, 100M points, 1M-point batches, Morton-shuffled",
+        points=100_000_000, batch=1_000_000, root_min=(0.0, 0.0, 0.0), root_size=1024.0),
+    "planes": dict(
+        desc="3 planes + 5% noise in the unit cube, 1M points, 100k-point batches",
+        points=1_000_000, batch=100_000, root_min=(0.0, 0.0, 0.0), root_size=1.0),
+}
+
+# Algorithmic bytes of k_sample_store per work item: read the 16-byte record,
+# write the 16-byte record and its 4-byte key into the leaf chunk; a spilled
+# item also reads its 4-byte key.
+SAMPLE_STORE_BYTES_PER_ITEM = 36
+SAMPLE_STORE_BYTES_PER_SPILLED = 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def generate(name, n):
+    import pointgen
+
+    w = WORKLOADS[name]
+    if name == "aerial":
+        return pointgen.aerial(n, seed=1, order="morton_shuffled", batch=w["batch"])
+    return pointgen.tiny_planes(n, seed=0)
+
+
+def cpu_baseline(points, batch, cfg_kw, budget_s=20.0):
+    """Sequential C oracle (one thread) on a prefix of the same batches."""
+    from oracle import LodConfig
+    from oracle.incremental import IncrementalOracle
+
+    cfg = LodConfig(root_min=cfg_kw["root_min"], root_size=cfg_kw["root_size"])
+    o = IncrementalOracle(cfg)
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(points) and time.perf_counter() - t0 < budget_s:
+        o.insert(points[done:done + batch])
+        done += min(batch, len(points) - done)
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": done / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done // batch} batches ({done} points) inserted in order, "
+                      f"{dt:.1f} s, sequential C inserter"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="aerial", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(nothing in this build uses a second GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_03567_amd import simlod
+
+    w = WORKLOADS[args.workload]
+    B = w["batch"]
+    nb_total = w["points"] // B
+    steps = min(args.steps, nb_total)
+    warm = min(args.warmup, nb_total)
+    t0 = time.perf_counter()
+    pts = generate(args.workload, w["points"])
+    log(f"generated {len(pts)} points in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.from_numpy(pts.view(np.uint8).reshape(-1)).to("cuda:0")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    cfg = simlod.make_config(root_min=w["root_min"], root_size=w["root_size"],
+                             max_nodes=1 << 20, arena_bytes=24 << 30, max_batch=B,
+                             spill_capacity=16 << 20, backlog_capacity=10_000_000)
+    tree = simlod.Octree(cfg)
+
+    def batch(i):
+        return dev[i * B * 16:(i + 1) * B * 16]
+
+    # warmup: W batches, plus one full untimed build that times every kernel
+    for i in range(warm):
+        tree.insert(batch(i), stream)
+    tree.sync()
+    tree.reset(stream)
+    simlod.set_kernel_timing(tree.handle, "all")
+    for i in range(steps):
+        tree.insert(batch(i), stream)
+    tree.sync()
+    per_kernel = simlod.get_kernel_times(tree.handle)
+    dominant = max(per_kernel, key=lambda k: per_kernel[k][1])
+    log("per-kernel (launches, total ms): " + json.dumps(per_kernel))
+    tree.reset(stream)
+    tree.sync()
+
+    # timed region: batches 0..K-1 into an empty octree; the dominant kernel
+    # is bracketed by events on the insertion stream, each pass by torch events
+    simlod.set_kernel_timing(tree.handle, [dominant])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        tree.insert(batch(i), stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = tree.stats()
+    kt = simlod.get_kernel_times(tree.handle)[dominant]
+    per_update_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    tree.close()
+
+    n_ins = steps * B
+    value = n_ins / elapsed
+    ms_per_step = elapsed * 1e3 / steps
+
+    roofline = None
+    if dominant == "sample_store" and kt[0] > 0:
+        work_items = n_ins + st["sum_spilled"]
+        alg_bytes = (SAMPLE_STORE_BYTES_PER_ITEM * work_items
+                     + SAMPLE_STORE_BYTES_PER_SPILLED * st["sum_spilled"])
+        avg_s = kt[1] / 1e3 / kt[0]
+        achieved = alg_bytes / kt[0] / avg_s / 1e9
+        roofline = {"kernel": "k_sample_store", "bound": "hbm", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "launches": kt[0], "avg_launch_us": round(avg_s * 1e6, 2),
+                    "bytes_per_launch": int(alg_bytes / kt[0])}
+    else:
+        roofline = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": None, "traffic": None, "launches": kt[0],
+                    "avg_launch_us": round(kt[1] * 1e3 / max(kt[0], 1), 2)}
+
+    result = {
+        "metric": "inserted points/sec (ms per 1M-point update)",
+        "value": round(value, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_1M_update": round(ms_per_step * 1e6 / B, 4),
+        "update_ms_p50": round(float(np.percentile(per_update_ms, 50)), 4),
+        "update_ms_p99": round(float(np.percentile(per_update_ms, 99)), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "points": n_ins, "batch": B, "leaf_capacity": 50_000,
+                   "grid": 128, "max_depth": 16, "chunk": 1000},
+        "octree": {k: st[k] for k in ("num_nodes", "num_inner", "num_points", "num_voxels",
+                                      "max_rounds", "sum_spilled", "sum_new_voxels")},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(pts, B, w, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

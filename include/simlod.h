@@ -1,0 +1,264 @@
+/*
+ * simlod.h -- C ABI of the MI355X octree LOD insertion library.
+ *
+ * The library keeps an octree level-of-detail structure resident in GPU
+ * memory and inserts batches of points into it incrementally, following
+ * "SimLOD: Simultaneous LOD Generation and Rendering" (Schuetz, Herzberger,
+ * Wimmer, arXiv 2310.03567), section "Incrementally Updating the Octree":
+ *
+ *   1. expand: count the points reaching each leaf and split leaves that
+ *      would exceed the leaf capacity, repeatedly, until none spills
+ *      (subsection "Expanding the Octree");
+ *   2. sample: project every point into the occupancy grid of each inner
+ *      node on its path and create a voxel for every newly occupied cell
+ *      (subsection "Voxel Sampling");
+ *   3. allocate chunks for the new points and voxels and store them
+ *      (subsections "Allocating Chunks" and "Storing Points and Voxels").
+ *
+ * Leaves hold the original points; inner nodes hold voxels sampled on an
+ * R^3 grid (section "Octree"); both live in linked lists of fixed-size chunks
+ * (section "Chunks and the Chunk Pool") carved out of one pre-allocated
+ * persistent buffer (section "Persistent Buffer").
+ *
+ * Determinism.  A voxel takes the colour of the point with the smallest key
+ * in its cell, key = position of the point in the cumulative insertion
+ * sequence (the paper keeps the first point that reaches an empty cell; on a
+ * GPU "first" is a race, so "first" is defined by key).  The resulting
+ * octree is then a pure function of the cumulative point sequence,
+ * independent of how it was cut into batches, and simlod_snapshot exports it
+ * in a canonical order that a CPU implementation reproduces bit for bit.
+ *
+ * Threading and streams.  A handle must be used by one host thread at a
+ * time.  Every call on a handle is ordered on the stream passed to it;
+ * callers that switch streams between calls must order the streams
+ * themselves.  Different handles are independent.
+ *
+ * Errors.  Every function returns SIMLOD_OK (0) or a negative SIMLOD_ERR_*
+ * code.  Capacity overflows detected on the device (node table, persistent
+ * buffer, spill buffer, voxel backlog, work list) are recorded in a sticky
+ * device status word and reported by a later call on the handle; the handle
+ * is then POISONED: its octree is undefined, every call except
+ * simlod_destroy, simlod_stats and simlod_status_string returns
+ * SIMLOD_ERR_POISONED, and no kernel touches memory outside the library's
+ * own buffers.
+ */
+#ifndef SIMLOD_H
+#define SIMLOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIMLOD_ABI_VERSION 1
+
+/* ---- status codes ---------------------------------------------------- */
+#define SIMLOD_OK 0
+#define SIMLOD_ERR_INVALID_ARGUMENT (-1) /* bad pointer, size or configuration   */
+#define SIMLOD_ERR_OUT_OF_MEMORY (-2)    /* device or host allocation failed     */
+#define SIMLOD_ERR_HIP (-3)              /* a HIP runtime call failed            */
+#define SIMLOD_ERR_CAPACITY (-4)         /* a device-side capacity overflowed    */
+#define SIMLOD_ERR_POISONED (-5)         /* handle unusable after an earlier error */
+#define SIMLOD_ERR_KEY_SPACE (-6)        /* more than 2^32 - 1 points in one octree */
+
+/* Bits of simlod_stats_data.status_bits (device-side overflow causes). */
+#define SIMLOD_OVF_NODES 0x1u   /* node table (max_nodes) full            */
+#define SIMLOD_OVF_ARENA 0x2u   /* persistent buffer (arena_bytes) full    */
+#define SIMLOD_OVF_SPILL 0x4u   /* spill buffer (spill_capacity) full      */
+#define SIMLOD_OVF_BACKLOG 0x8u /* voxel backlog (backlog_capacity) full   */
+#define SIMLOD_OVF_WORK 0x10u   /* expansion work list full                */
+#define SIMLOD_OVF_HASH 0x20u   /* voxel claim table probe limit reached   */
+
+/* ---- records ---------------------------------------------------------- */
+
+/* One point: XYZRGBA, 3 x float32 + 4 x uint8 = 16 bytes, the record format
+ * the update consumes (section "Data Sets", SIM format).  Voxels use the
+ * same record with xyz at the centre of their grid cell (section "Octree"). */
+typedef struct simlod_point {
+    float x, y, z;
+    uint8_t r, g, b, a;
+} simlod_point;
+
+/* ---- configuration ----------------------------------------------------- */
+
+/* Octree parameters and capacities.  Fill with simlod_default_config and
+ * override what is needed.
+ *
+ * root_min, root_size  Cubic domain of the octree, fixed at creation (a
+ *                      streamed cloud's final bounds are unknown).  Integer
+ *                      coordinates: K = max_depth + grid_bits bits per axis,
+ *                      scale = fl32(2^K / root_size),
+ *                      q = clamp(floor(fl32(fl32(v - root_min) * scale)),
+ *                      0, 2^K - 1), NaN -> 0.  Points outside the domain are
+ *                      clamped for placement only; their records are stored
+ *                      unchanged.
+ * leaf_capacity        T: a leaf splits when it would hold more than T
+ *                      points (section "Octree": 50,000).
+ * grid_bits            r: inner nodes sample on an R^3 grid, R = 2^r
+ *                      (section "Voxel Sampling Grid": 128^3, r = 7); 0..8.
+ * max_depth            Dmax: depth of the deepest possible leaf (root = 0);
+ *                      nodes at Dmax never split.  max_depth + grid_bits
+ *                      must be <= 24, max_depth <= 21.
+ * chunk_capacity       C: records per chunk (section "Chunks and the Chunk
+ *                      Pool": 1000).  Changes layout only, never results.
+ * max_nodes            Node table capacity (>= 9).
+ * arena_bytes          Persistent buffer for chunks, occupancy grids and
+ *                      chunk tables; 0 = 90% of the free device memory left
+ *                      after the other buffers (section "Persistent Buffer").
+ * max_batch            Largest batch processed in one pass; larger inserts
+ *                      are cut into consecutive passes of at most max_batch
+ *                      points, which gives the identical octree.
+ * spill_capacity       Points of split leaves re-inserted in one pass
+ *                      (section "Expanding the Octree", spill buffer).
+ * backlog_capacity     New voxels in one pass (section "Voxel Sampling"
+ *                      suggests 10M).
+ * device               HIP device ordinal.
+ */
+typedef struct simlod_config {
+    float root_min[3];
+    float root_size;
+    uint32_t leaf_capacity;
+    uint32_t grid_bits;
+    uint32_t max_depth;
+    uint32_t chunk_capacity;
+    uint32_t max_nodes;
+    uint32_t reserved0;
+    uint64_t arena_bytes;
+    uint64_t max_batch;
+    uint64_t spill_capacity;
+    uint64_t backlog_capacity;
+    int32_t device;
+    uint32_t reserved1;
+} simlod_config;
+
+/* Node record of the canonical export: preorder, children in octant order
+ * 0..7 (octant bit 0 = x, bit 1 = y, bit 2 = z), all 8 children of an inner
+ * node present.  path = 1 for the root, parent_path * 8 + octant below it.
+ * count = points of a leaf or voxels of an inner node; the node's records
+ * are records[first .. first + count), sorted by key.  24 bytes. */
+typedef struct simlod_node_record {
+    uint64_t path;
+    uint64_t first;
+    uint32_t count;
+    uint8_t depth;
+    uint8_t is_leaf;
+    uint16_t reserved;
+} simlod_node_record;
+
+/* Canonical export buffers (two-call pattern, see simlod_snapshot). */
+typedef struct simlod_snapshot_buffers {
+    uint64_t num_nodes;         /* out */
+    uint64_t num_records;       /* out: num_points + num_voxels */
+    uint64_t num_points;        /* out */
+    uint64_t num_voxels;        /* out */
+    simlod_node_record* nodes;  /* in: host buffer of num_nodes, or NULL */
+    simlod_point* records;      /* in: host buffer of num_records, or NULL */
+    uint32_t* keys;             /* in: host buffer of num_records, or NULL; a
+                                   leaf point's own key, or the key of the
+                                   point that coloured a voxel */
+} simlod_snapshot_buffers;
+
+/* Counters of a handle (simlod_stats). */
+typedef struct simlod_stats_data {
+    uint64_t num_nodes, num_leaves, num_inner;
+    uint64_t num_points, num_voxels;
+    uint64_t chunks_in_use;      /* sum over nodes of ceil(count / C)          */
+    uint64_t chunks_pooled;      /* freed chunks waiting for reuse             */
+    uint64_t arena_bytes_used, arena_bytes_total;
+    uint64_t batches;            /* insertion passes so far                    */
+    uint64_t points_inserted;
+    uint64_t last_rounds;        /* count/split rounds of the last pass        */
+    uint64_t last_spilled;       /* points re-inserted from split leaves       */
+    uint64_t last_new_voxels;    /* voxels created by the last pass            */
+    uint64_t max_rounds, max_spilled, max_new_voxels; /* high-water marks     */
+    uint64_t sum_rounds, sum_spilled, sum_new_voxels; /* totals over passes   */
+    uint32_t status_bits;        /* SIMLOD_OVF_* bits, 0 when healthy          */
+    int32_t poisoned;
+} simlod_stats_data;
+
+/* Per-kernel timing, recorded with HIP events around each launch when
+ * enabled by simlod_set_kernel_timing.  Index = SIMLOD_KERNEL_*. */
+#define SIMLOD_KERNEL_COUNT 0        /* expansion: count points per leaf   */
+#define SIMLOD_KERNEL_SPLIT 1        /* expansion: split / finalize leaves */
+#define SIMLOD_KERNEL_ALLOC_POINTS 2 /* chunk allocation for leaves        */
+#define SIMLOD_KERNEL_SAMPLE_STORE 3 /* voxel claims + point stores        */
+#define SIMLOD_KERNEL_ALLOC_VOXELS 4 /* chunk allocation for inner nodes   */
+#define SIMLOD_KERNEL_STORE_VOXELS 5 /* voxel stores                       */
+#define SIMLOD_KERNEL_FINISH 6       /* per-pass bookkeeping               */
+#define SIMLOD_NUM_KERNELS 7
+typedef struct simlod_kernel_times {
+    uint64_t launches[SIMLOD_NUM_KERNELS];
+    double total_ms[SIMLOD_NUM_KERNELS];
+} simlod_kernel_times;
+
+typedef struct simlod_octree simlod_octree; /* opaque handle */
+
+/* ---- functions --------------------------------------------------------- */
+
+/* Fills *cfg with the paper's parameters (T = 50,000, 128^3 grid, chunks of
+ * 1,000, section "Octree") and default capacities: unit cube at the origin,
+ * max_depth 16, 2^20 nodes, arena 0 (= 90% of free memory), max_batch 10M,
+ * spill 16M, backlog 10M (section "Voxel Sampling"), device 0. */
+int simlod_default_config(simlod_config* cfg);
+
+/* Creates an empty octree (a single empty root leaf) on cfg->device.  All
+ * device memory is allocated here; inserting never allocates.  *out is
+ * written only on success.  Errors: INVALID_ARGUMENT (NULL pointers,
+ * parameters outside the ranges above), OUT_OF_MEMORY, HIP. */
+int simlod_create(const simlod_config* cfg, simlod_octree** out);
+
+/* Inserts n points (the next n keys of the cumulative sequence).
+ * pts: device or host pointer to n simlod_point records (16-byte aligned for
+ * device memory); host memory is copied to a library staging buffer first.
+ * The points are borrowed until the stream work completes and never
+ * retained.  stream: hipStream_t (NULL = the default stream); the call only
+ * enqueues work and returns.  n = 0 is a no-op.
+ * Errors: INVALID_ARGUMENT (NULL handle, NULL pts with n > 0), KEY_SPACE,
+ * POISONED, CAPACITY (an earlier pass overflowed; handle now poisoned), HIP. */
+int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, void* stream);
+
+/* Canonical export.  Synchronizes the handle's last stream.  Call with all
+ * three buffer pointers NULL to obtain the sizes, then with host buffers of
+ * at least those sizes (the octree must not change in between).  The
+ * library allocates temporary device memory here.
+ * Errors: INVALID_ARGUMENT (only some buffers NULL), POISONED, CAPACITY,
+ * OUT_OF_MEMORY, HIP. */
+int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s);
+
+/* Counters; synchronizes the handle's last stream.  Works on a poisoned
+ * handle (status_bits tells why). */
+int simlod_stats(simlod_octree* h, simlod_stats_data* st);
+
+/* Waits for all work enqueued on the handle; reports device-side errors. */
+int simlod_sync(simlod_octree* h);
+
+/* Empties the octree (single empty root, key sequence restarts at 0) and
+ * keeps all allocations; clears a poisoned state.  Enqueued on stream. */
+int simlod_reset(simlod_octree* h, void* stream);
+
+/* Frees everything; safe on a poisoned handle; NULL is a no-op. */
+int simlod_destroy(simlod_octree* h);
+
+/* Selects the kernels whose launches later passes bracket with HIP events on
+ * the pass's stream: bit k of kernel_mask = SIMLOD_KERNEL_k (0 disables,
+ * 0x7F times all).  Clears the accumulated times. */
+int simlod_set_kernel_timing(simlod_octree* h, uint32_t kernel_mask);
+
+/* Synchronizes and returns the times accumulated since timing was enabled. */
+int simlod_get_kernel_times(simlod_octree* h, simlod_kernel_times* out);
+
+/* Static description of a status code. */
+const char* simlod_status_string(int code);
+
+/* Text naming the HIP call behind the calling thread's most recent
+ * SIMLOD_ERR_HIP or SIMLOD_ERR_OUT_OF_MEMORY ("" if none); valid until the
+ * thread's next library call. */
+const char* simlod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMLOD_H */

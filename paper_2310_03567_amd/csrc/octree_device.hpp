@@ -1,0 +1,206 @@
+// Device-side layout of one octree and the wave-level helpers its kernels use.
+//
+// Everything an insertion pass touches lives in device memory allocated at
+// creation; the kernels receive it as one by-value `DevTree`.
+//
+// Node table (structure of arrays, capacity max_nodes, root = node 0):
+//   child[n]    first of the node's 8 consecutive children, 0 for a leaf
+//               (node 0 is the root and never a child, so 0 is free)
+//   count[n]    points of a leaf / voxels of an inner node; during the store
+//               passes it is also the slot counter (section "Storing Points
+//               and Voxels": numPoints / numVoxels)
+//   cnt[n]      expansion counter of the current round (section "Expanding
+//               the Octree": point counter), zero outside a round
+//   birth[n]    epoch of the round whose split created the node
+//   geo[n]      {origin x, origin y, origin z, depth}, origin in integer
+//               coordinates (units of 2^-K of the root size)
+//   grid[n]     arena block of the R^3 occupancy bitmap (inner nodes)
+//   tab[n], tabcap[n], nchunks[n]
+//               arena block, capacity and length of the node's chunk table:
+//               the ids of its chunks in list order, so chunk slot/C is one
+//               load away (the chunks are also linked, see below)
+//   newv[n]     voxels claimed for the node in the current pass
+//
+// Persistent buffer ("arena", section "Persistent Buffer"): one allocation
+// carved into 256-byte blocks by an atomic bump counter; chunks, occupancy
+// grids and chunk tables are addressed by their first block (u32).  A chunk
+// of capacity C holds C 16-byte records, then C u32 keys, then the u32 block
+// id of the next chunk of the same node (0xFFFFFFFF ends the list), the
+// linked list of section "Chunks and the Chunk Pool".  Freed chunks go to a
+// stack of block ids (the chunk pool) and are reused before the bump counter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace simlod {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef int32_t i32;
+
+constexpr u32 kNone = 0xFFFFFFFFu;
+constexpr u64 kEmptyTag = ~0ull;
+constexpr u32 kBlockBytes = 256;
+constexpr int kMaxRounds = 24;  // >= max_depth + 1
+
+// Device-resident counters of one octree.
+struct Counters {
+    u32 node_count;
+    u32 status;          // sticky SIMLOD_OVF_* bits
+    u32 arena_top;       // blocks handed out
+    i32 pool_top;        // chunk ids on the pool stack (negative = empty)
+    u32 spill_count;     // points moved to the spill buffer this pass
+    u32 final_count;     // leaves finalized this pass
+    u32 vtouched_count;  // inner nodes that claimed voxels this pass
+    u32 claim_count;     // voxels claimed this pass (backlog length)
+    u32 touched_count[2];
+    u32 active_count[2];
+    u32 split_any[kMaxRounds + 2];
+    // statistics of the last pass and high-water marks
+    u32 last_rounds, last_spilled, last_new_voxels;
+    u32 max_rounds, max_spilled, max_new_voxels;
+    u64 sum_spilled, sum_new_voxels, sum_rounds;
+};
+
+struct DevTree {
+    // node table
+    u32* child;
+    u32* count;
+    u32* cnt;
+    u32* birth;
+    uint4* geo;
+    u32* grid;
+    u32* tab;
+    u32* tabcap;
+    u32* nchunks;
+    u32* newv;
+    u32 max_nodes;
+    Counters* ctr;
+    // persistent buffer and chunk pool
+    uint8_t* arena;
+    u32 arena_blocks;
+    u32* pool;
+    u32 pool_cap;
+    // per-pass work buffers
+    uint4* spill_rec;
+    u32* spill_key;
+    u32 spill_cap;
+    u32* touched[2];
+    uint2* final_list;   // {leaf, points added}
+    u32* vtouched;       // inner nodes with new voxels
+    u32* active[2];      // work-list indices still being counted
+    u32 active_cap;
+    u64* htag;           // voxel claim table: (node << 24 | cell) or empty
+    u64* hval;           // (key << 32 | rgba), min-reduced
+    u32 hmask;
+    u32* claims;         // claim-table slots of the voxels claimed this pass
+    u32 claim_cap;
+    // geometry and parameters
+    float mn[3];
+    float size;
+    float scale;
+    u32 K, r, R, Dmax, T, C;
+    u32 chunk_blocks, grid_blocks, grid_words;
+};
+
+__device__ __forceinline__ uint8_t* block_ptr(const DevTree& t, u32 blk) {
+    return t.arena + (u64)blk * kBlockBytes;
+}
+__device__ __forceinline__ uint4* chunk_recs(const DevTree& t, u32 blk) {
+    return reinterpret_cast<uint4*>(block_ptr(t, blk));
+}
+__device__ __forceinline__ u32* chunk_keys(const DevTree& t, u32 blk) {
+    return reinterpret_cast<u32*>(block_ptr(t, blk) + (u64)t.C * 16u);
+}
+__device__ __forceinline__ u32* chunk_next(const DevTree& t, u32 blk) {
+    return reinterpret_cast<u32*>(block_ptr(t, blk) + (u64)t.C * 20u);
+}
+__device__ __forceinline__ u32* table_of(const DevTree& t, u32 node) {
+    return reinterpret_cast<u32*>(block_ptr(t, t.tab[node]));
+}
+__device__ __forceinline__ u32* grid_of(const DevTree& t, u32 node) {
+    return reinterpret_cast<u32*>(block_ptr(t, t.grid[node]));
+}
+
+// Integer coordinate along one axis.  The subtraction and the product are
+// separately rounded (explicit _rn intrinsics, so contraction can never fuse
+// them); negative and NaN map to 0, everything at or beyond the far face to
+// 2^K - 1.
+__device__ __forceinline__ u32 quantize(float v, float mn, float scale, u32 K) {
+    float u = __fmul_rn(__fsub_rn(v, mn), scale);
+    if (!(u >= 0.0f)) return 0u;
+    float f = floorf(u);
+    float qmax = (float)((1u << K) - 1u);
+    f = fminf(f, qmax);
+    return (u32)f;
+}
+
+// Centre of global cell g at depth d along one axis:
+// fl32(mn + fl32(fl32(g + 0.5) * h_d)), h_d = size * 2^-(r + d).
+__device__ __forceinline__ float cell_centre(u32 g, float mn, float size, u32 r, u32 d) {
+    float h = ldexpf(size, -(int)(r + d));
+    return __fadd_rn(mn, __fmul_rn(__fadd_rn((float)g, 0.5f), h));
+}
+
+__device__ __forceinline__ u32 octant_of(u32 qx, u32 qy, u32 qz, u32 bit) {
+    return ((qx >> bit) & 1u) | (((qy >> bit) & 1u) << 1) | (((qz >> bit) & 1u) << 2);
+}
+
+__device__ __forceinline__ void set_status(const DevTree& t, u32 bits) {
+    atomicOr(&t.ctr->status, bits);
+}
+
+__device__ __forceinline__ u32 lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 lanes_below(u32 lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+// Wave-aggregated append: every lane with `pred` gets a distinct slot of
+// *counter, with one atomic per wave.  Must be reached by the whole wave.
+__device__ __forceinline__ u32 wave_append(u32* counter, bool pred) {
+    u64 m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    u32 lane = lane_id();
+    int leader = __ffsll((long long)m) - 1;
+    u32 base = 0;
+    if ((int)lane == leader) base = atomicAdd(counter, (u32)__popcll(m));
+    base = __shfl(base, leader);
+    return base + (u32)__popcll(m & lanes_below(lane));
+}
+
+// Run-length aggregation over consecutive lanes holding equal `id`
+// (ids of kNone are excluded).  Returns for each lane its run head and the
+// run length at the head.  Must be reached by the whole wave.
+struct Run {
+    int head;
+    u32 len;   // valid at the head lane
+    u32 rank;  // lane - head
+};
+__device__ __forceinline__ Run lane_runs(u32 id) {
+    u32 lane = lane_id();
+    u32 prev = __shfl_up(id, 1);
+    bool is_head = (lane == 0) || (prev != id);
+    u64 heads = __ballot(is_head);
+    u64 upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    int head = 63 - __clzll((long long)(heads & upto));
+    u64 above = (lane == 63) ? 0ull : (heads >> (lane + 1));
+    u32 next = above ? (lane + 1 + (u32)__ffsll((long long)above) - 1) : 64u;
+    Run r;
+    r.head = head;
+    r.len = next - lane;
+    r.rank = lane - (u32)head;
+    return r;
+}
+
+__device__ __forceinline__ u64 mix64(u64 x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+}  // namespace simlod

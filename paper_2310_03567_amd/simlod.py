@@ -1,0 +1,298 @@
+"""ctypes binding of libsimlod.so (include/simlod.h): argument marshalling only.
+
+Every step of an insertion runs in the library's HIP kernels; this module
+converts Python arguments (torch CUDA tensors, numpy arrays, streams) into the
+C ABI's plain pointers and sizes.  There is no fallback: if the shared
+library is missing or cannot be loaded, importing this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsimlod.so")
+
+OK = 0
+ERR_INVALID_ARGUMENT = -1
+ERR_OUT_OF_MEMORY = -2
+ERR_HIP = -3
+ERR_CAPACITY = -4
+ERR_POISONED = -5
+ERR_KEY_SPACE = -6
+
+OVF_NODES, OVF_ARENA, OVF_SPILL, OVF_BACKLOG, OVF_WORK, OVF_HASH = 1, 2, 4, 8, 16, 32
+
+KERNEL_NAMES = ("count", "split", "alloc_points", "sample_store", "alloc_voxels",
+                "store_voxels", "finish")
+
+# 16-byte point record: float32 x, y, z and r, g, b, a bytes (rgba as one
+# little-endian u32: r in the low byte).
+POINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("rgba", "<u4")])
+NODE_DTYPE = np.dtype([("path", "<u8"), ("first", "<u8"), ("count", "<u4"), ("depth", "u1"),
+                       ("is_leaf", "u1"), ("reserved", "<u2")])
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("root_min", ctypes.c_float * 3),
+        ("root_size", ctypes.c_float),
+        ("leaf_capacity", ctypes.c_uint32),
+        ("grid_bits", ctypes.c_uint32),
+        ("max_depth", ctypes.c_uint32),
+        ("chunk_capacity", ctypes.c_uint32),
+        ("max_nodes", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("arena_bytes", ctypes.c_uint64),
+        ("max_batch", ctypes.c_uint64),
+        ("spill_capacity", ctypes.c_uint64),
+        ("backlog_capacity", ctypes.c_uint64),
+        ("device", ctypes.c_int32),
+        ("reserved1", ctypes.c_uint32),
+    ]
+
+
+class SnapshotBuffers(ctypes.Structure):
+    _fields_ = [
+        ("num_nodes", ctypes.c_uint64),
+        ("num_records", ctypes.c_uint64),
+        ("num_points", ctypes.c_uint64),
+        ("num_voxels", ctypes.c_uint64),
+        ("nodes", ctypes.c_void_p),
+        ("records", ctypes.c_void_p),
+        ("keys", ctypes.c_void_p),
+    ]
+
+
+class StatsData(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "num_nodes", "num_leaves", "num_inner", "num_points", "num_voxels", "chunks_in_use",
+        "chunks_pooled", "arena_bytes_used", "arena_bytes_total", "batches", "points_inserted",
+        "last_rounds", "last_spilled", "last_new_voxels", "max_rounds", "max_spilled",
+        "max_new_voxels", "sum_rounds", "sum_spilled", "sum_new_voxels")] + [("status_bits", ctypes.c_uint32), ("poisoned", ctypes.c_int32)]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64 * 7), ("total_ms", ctypes.c_double * 7)]
+
+
+EXPORTS = {
+    "simlod_default_config": ([ctypes.POINTER(Config)], ctypes.c_int),
+    "simlod_create": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "simlod_insert_batch": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p],
+                            ctypes.c_int),
+    "simlod_snapshot": ([ctypes.c_void_p, ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
+    "simlod_stats": ([ctypes.c_void_p, ctypes.POINTER(StatsData)], ctypes.c_int),
+    "simlod_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "simlod_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "simlod_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "simlod_set_kernel_timing": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
+    "simlod_get_kernel_times": ([ctypes.c_void_p, ctypes.POINTER(KernelTimes)], ctypes.c_int),
+    "simlod_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "simlod_last_error": ([], ctypes.c_char_p),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+# torch ships its own HIP runtime with the same SONAME (libamdhip64.so.7).
+# Loading torch first makes the dynamic linker bind the library to that one
+# runtime, so torch's streams and device pointers are valid here; loading the
+# library first would put two HIP runtimes into the process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # torch-free use (e.g. host-only checks)
+    pass
+lib = ctypes.CDLL(LIB_PATH)
+for _name, (_args, _res) in EXPORTS.items():
+    _fn = getattr(lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+class SimlodError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+def status_string(code: int) -> str:
+    return lib.simlod_status_string(code).decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != OK:
+        detail = lib.simlod_last_error().decode() if code in (ERR_HIP, ERR_OUT_OF_MEMORY) else ""
+        raise SimlodError(code, f"{what} [{detail}]" if detail else what)
+
+
+def default_config() -> Config:
+    cfg = Config()
+    _check(lib.simlod_default_config(ctypes.byref(cfg)), "simlod_default_config")
+    return cfg
+
+
+def make_config(root_min=(0.0, 0.0, 0.0), root_size=1.0, leaf_capacity=50_000, grid_bits=7,
+                max_depth=16, chunk_capacity=1000, max_nodes=None, arena_bytes=None,
+                max_batch=None, spill_capacity=None, backlog_capacity=None, device=0) -> Config:
+    cfg = default_config()
+    cfg.root_min[:] = [float(v) for v in root_min]
+    cfg.root_size = float(root_size)
+    cfg.leaf_capacity = int(leaf_capacity)
+    cfg.grid_bits = int(grid_bits)
+    cfg.max_depth = int(max_depth)
+    cfg.chunk_capacity = int(chunk_capacity)
+    cfg.device = int(device)
+    for name, v in (("max_nodes", max_nodes), ("arena_bytes", arena_bytes),
+                    ("max_batch", max_batch), ("spill_capacity", spill_capacity),
+                    ("backlog_capacity", backlog_capacity)):
+        if v is not None:
+            setattr(cfg, name, int(v))
+    return cfg
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        try:
+            import torch
+
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream or None
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return getattr(stream, "cuda_stream", None) or None
+
+
+def _points_ptr(points):
+    """(pointer, count, keepalive) for a torch tensor or numpy array of records."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(points, torch.Tensor):
+        if not points.is_contiguous():
+            raise ValueError("points tensor must be contiguous")
+        nbytes = points.numel() * points.element_size()
+        if nbytes % 16:
+            raise ValueError("points tensor must hold whole 16-byte records")
+        return points.data_ptr(), nbytes // 16, points
+    arr = np.ascontiguousarray(points)
+    if arr.dtype != POINT_DTYPE:
+        if arr.nbytes % 16:
+            raise ValueError("points array must hold whole 16-byte records")
+        arr = arr.view(np.uint8).reshape(-1)
+    return arr.ctypes.data, arr.nbytes // 16, arr
+
+
+def create(cfg: Config) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.simlod_create(ctypes.byref(cfg), ctypes.byref(h)), "simlod_create")
+    return h.value
+
+
+def insert_batch(handle: int, points, stream=None) -> None:
+    ptr, n, keep = _points_ptr(points)
+    _check(lib.simlod_insert_batch(handle, ptr if n else None, n, _stream_ptr(stream)),
+           "simlod_insert_batch")
+    del keep
+
+
+def snapshot(handle: int):
+    """Canonical export: (nodes NODE_DTYPE, records POINT_DTYPE, keys uint32)."""
+    s = SnapshotBuffers()
+    _check(lib.simlod_snapshot(handle, ctypes.byref(s)), "simlod_snapshot (sizes)")
+    nodes = np.zeros(s.num_nodes, dtype=NODE_DTYPE)
+    records = np.zeros(s.num_records, dtype=POINT_DTYPE)
+    keys = np.zeros(s.num_records, dtype=np.uint32)
+    s.nodes = nodes.ctypes.data
+    s.records = records.ctypes.data
+    s.keys = keys.ctypes.data
+    _check(lib.simlod_snapshot(handle, ctypes.byref(s)), "simlod_snapshot")
+    return nodes[: s.num_nodes], records[: s.num_records], keys[: s.num_records]
+
+
+def stats(handle: int) -> dict:
+    st = StatsData()
+    _check(lib.simlod_stats(handle, ctypes.byref(st)), "simlod_stats")
+    return {name: getattr(st, name) for name, _ in StatsData._fields_}
+
+
+def sync(handle: int) -> None:
+    _check(lib.simlod_sync(handle), "simlod_sync")
+
+
+def reset(handle: int, stream=None) -> None:
+    _check(lib.simlod_reset(handle, _stream_ptr(stream)), "simlod_reset")
+
+
+def destroy(handle: int) -> None:
+    _check(lib.simlod_destroy(handle), "simlod_destroy")
+
+
+def set_kernel_timing(handle: int, kernels=()) -> None:
+    """Times the named kernels (see KERNEL_NAMES); empty disables."""
+    if kernels == "all":
+        kernels = KERNEL_NAMES
+    mask = 0
+    for k in kernels:
+        mask |= 1 << KERNEL_NAMES.index(k)
+    _check(lib.simlod_set_kernel_timing(handle, mask), "simlod_set_kernel_timing")
+
+
+def get_kernel_times(handle: int) -> dict:
+    kt = KernelTimes()
+    _check(lib.simlod_get_kernel_times(handle, ctypes.byref(kt)), "simlod_get_kernel_times")
+    return {name: (int(kt.launches[i]), float(kt.total_ms[i])) for i, name in enumerate(KERNEL_NAMES)}
+
+
+@dataclass
+class Snapshot:
+    nodes: np.ndarray
+    records: np.ndarray
+    keys: np.ndarray
+
+
+class Octree:
+    """Owning wrapper around one handle."""
+
+    def __init__(self, cfg: Config | None = None, **kw):
+        self.cfg = cfg if cfg is not None else make_config(**kw)
+        self.handle = create(self.cfg)
+
+    def insert(self, points, stream=None) -> None:
+        insert_batch(self.handle, points, stream)
+
+    def snapshot(self) -> Snapshot:
+        return Snapshot(*snapshot(self.handle))
+
+    def stats(self) -> dict:
+        return stats(self.handle)
+
+    def sync(self) -> None:
+        sync(self.handle)
+
+    def reset(self, stream=None) -> None:
+        reset(self.handle, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

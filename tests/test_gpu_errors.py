@@ -1,0 +1,106 @@
+"""Failure handling forced from the host: capacities shrunk in the config make
+the device-side bounds checks trip; every kernel still exits normally, the
+error surfaces on a later call as SIMLOD_ERR_CAPACITY and the handle is
+poisoned until reset."""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import POINT_DTYPE, LodConfig, assert_trees_equal
+from oracle import definition as O1
+from tests.gpu_util import canonical, log, make_octree, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _cloud(n, seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(n, dtype=POINT_DTYPE)
+    xyz = (rng.random((n, 3)) ** 3).astype(np.float32)
+    p["x"], p["y"], p["z"] = xyz.T
+    p["rgba"] = rng.integers(0, 2**32, n, dtype=np.uint32)
+    return p
+
+
+@pytest.mark.parametrize("caps,bit", [
+    (dict(max_nodes=17), 0x1),
+    (dict(arena_bytes=1 << 20), 0x2),
+    (dict(spill_capacity=10), 0x4),
+    (dict(backlog_capacity=50), 0x8),
+])
+def test_capacity_overflow_poisons_the_handle(caps, bit):
+    from paper_2310_03567_amd import simlod
+
+    cfg = LodConfig(leaf_capacity=20, grid_bits=3, max_depth=8, chunk_capacity=4)
+    p = _cloud(20_000, 1)
+    log(f"case: overflow {caps}")
+    with make_octree(cfg, **caps) as tree:
+        def run():  # the error may surface at the second insert or at sync
+            tree.insert(to_device(p[:100]))
+            tree.insert(to_device(p[100:]))
+            tree.sync()
+
+        with pytest.raises(simlod.SimlodError) as ei:
+            run()
+        assert ei.value.code == simlod.ERR_CAPACITY
+        st = tree.stats()
+        assert st["poisoned"] == 1 and st["status_bits"] & bit
+        with pytest.raises(simlod.SimlodError) as ei:
+            tree.insert(to_device(p[:10]))
+        assert ei.value.code == simlod.ERR_POISONED
+        with pytest.raises(simlod.SimlodError) as ei:
+            tree.snapshot()
+        assert ei.value.code == simlod.ERR_POISONED
+        # reset clears the poison; a workload that fits works again
+        tree.reset()
+        q = p[:15]
+        tree.insert(to_device(q))
+        assert_trees_equal(canonical(tree), O1.build(q, cfg))
+
+
+def test_key_space_is_checked_on_the_host():
+    from paper_2310_03567_amd import simlod
+
+    cfg = LodConfig(leaf_capacity=20, grid_bits=3, max_depth=8)
+    with make_octree(cfg) as tree:
+        dev = to_device(_cloud(4, 2))
+        rc = simlod.lib.simlod_insert_batch(tree.handle, dev.data_ptr(), 1 << 32, None)
+        assert rc == simlod.ERR_KEY_SPACE
+        tree.insert(dev)
+        assert tree.stats()["points_inserted"] == 4
+
+
+def test_misaligned_device_pointer_rejected():
+    from paper_2310_03567_amd import simlod
+
+    cfg = LodConfig(leaf_capacity=20, grid_bits=3, max_depth=8)
+    with make_octree(cfg) as tree:
+        dev = to_device(_cloud(8, 3))
+        rc = simlod.lib.simlod_insert_batch(tree.handle, dev.data_ptr() + 4, 2, None)
+        assert rc == simlod.ERR_INVALID_ARGUMENT
+
+
+def test_snapshot_two_call_contract():
+    from paper_2310_03567_amd import simlod
+
+    cfg = LodConfig(leaf_capacity=20, grid_bits=3, max_depth=8)
+    with make_octree(cfg) as tree:
+        tree.insert(to_device(_cloud(500, 4)))
+        s = simlod.SnapshotBuffers()
+        assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.OK
+        assert s.num_records == s.num_points + s.num_voxels and s.num_points == 500
+        buf = np.zeros(1, dtype=simlod.NODE_DTYPE)
+        s.nodes = buf.ctypes.data  # only one of three buffers given
+        assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.ERR_INVALID_ARGUMENT

@@ -1,0 +1,198 @@
+"""Bit-exact parity of the HIP insertion path with the CPU oracle.
+
+Every test inserts seeded synthetic points through the C ABI (via the ctypes
+binding) and compares the canonical snapshot with the oracle element by
+element: node records, point/voxel records and keys must be identical.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import POINT_DTYPE, LodConfig, assert_trees_equal
+from oracle import definition as O1
+from oracle.incremental import IncrementalOracle
+from tests.golden_util import check_against_expected, load_fig_update
+from tests.gpu_util import canonical, insert_batches, log, make_octree, to_device
+from tests.invariants import check_invariants
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_03567_amd import simlod  # noqa: F401  (fails loudly if not built)
+
+
+def _pts(xyz, rgba):
+    xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
+    p = np.zeros(len(xyz), dtype=POINT_DTYPE)
+    p["x"], p["y"], p["z"] = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    p["rgba"] = rgba
+    return p
+
+
+def test_hand_worked_example():
+    cfg, batches, expected = load_fig_update()
+    log("case: fig-update analogue T=5 C=2")
+    with make_octree(cfg) as tree:
+        seen = []
+        for b, e in zip(batches, expected):
+            seen.append(b)
+            tree.insert(to_device(b))
+            got = canonical(tree)
+            allp = np.concatenate(seen)
+            check_against_expected(got, allp, e)
+            st = tree.stats()
+            assert st["chunks_in_use"] == e["chunks"]
+            assert st["status_bits"] == 0
+
+
+def _tiny(rng, n):
+    mode = rng.integers(0, 4)
+    if mode == 0:
+        xyz = rng.random((n, 3))
+    elif mode == 1:
+        xyz = rng.integers(0, 8, (n, 3)) / 8.0
+    elif mode == 2:
+        xyz = rng.random((n, 3)) ** 4
+    else:
+        xyz = np.repeat(rng.random((n // 10 + 1, 3)), 10, axis=0)[:n]
+    if n and rng.random() < 0.3:
+        xyz[rng.integers(0, n)] = [np.nan, -3.0, 7.0]
+        xyz[rng.integers(0, n)] = [np.inf, 0.5, -np.inf]
+    return _pts(xyz, rng.integers(0, 2**32, n, dtype=np.uint32))
+
+
+def test_many_tiny_configurations():
+    rng = np.random.default_rng(11)
+    cases = 0
+    for T in (1, 2, 5, 17):
+        for r in (0, 1, 2, 3):
+            for dmax in (0, 1, 3, 6):
+                C = int(rng.choice([1, 2, 3, 7, 1000]))
+                cfg = LodConfig(leaf_capacity=T, grid_bits=r, max_depth=dmax, chunk_capacity=C)
+                n = int(rng.integers(0, 300))
+                p = _tiny(rng, n)
+                parts = np.diff(np.unique(np.concatenate([[0, n], rng.integers(0, n + 1, 4)])))
+                log(f"case: tiny T={T} r={r} Dmax={dmax} C={C} n={n} parts={parts.tolist()}")
+                with make_octree(cfg, max_nodes=1 << 14, arena_bytes=64 << 20) as tree:
+                    insert_batches(tree, to_device(p), parts.tolist())
+                    got = canonical(tree)
+                    st = tree.stats()
+                assert_trees_equal(got, O1.build(p, cfg), f"T={T} r={r} Dmax={dmax} C={C} n={n}")
+                assert st["status_bits"] == 0
+                assert st["chunks_in_use"] == sum(-(-int(c) // C) for c in got.nodes["count"])
+                cases += 1
+    assert cases == 64
+
+
+def test_every_batch_matches_sequential_oracle_on_planes():
+    """Plain method, tiny workload shape (1M points on 3 planes + 5% noise,
+    10 batches of 100k, T = 50k, 128^3 grid, Dmax 16): snapshot after every
+    batch equals the sequential oracle's octree after the same batches."""
+    import pointgen
+
+    p = pointgen.tiny_planes(1_000_000, seed=0)
+    cfg = LodConfig()
+    dev = to_device(p)
+    o = IncrementalOracle(cfg)
+    with make_octree(cfg, arena_bytes=2 << 30) as tree:
+        for k in range(10):
+            log(f"case: planes batch {k}")
+            b = slice(k * 100_000, (k + 1) * 100_000)
+            tree.insert(dev[b.start * 16:b.stop * 16])
+            o.insert(p[b])
+            assert_trees_equal(canonical(tree), o.canonical(), f"after batch {k}")
+        st = tree.stats()
+    assert st["num_points"] == 1_000_000 and st["status_bits"] == 0
+    assert st["num_inner"] >= 1
+
+
+@pytest.mark.parametrize("parts", [[1_000_000], [250_000] * 4, [1, 99_999, 400_000, 500_000],
+                                   [333_333, 333_333, 333_334]])
+def test_batch_partition_invariance_on_planes(parts):
+    import pointgen
+
+    p = pointgen.tiny_planes(1_000_000, seed=3)
+    cfg = LodConfig(leaf_capacity=20_000)
+    ref = O1.build(p, cfg)
+    log(f"case: partition {parts}")
+    with make_octree(cfg, arena_bytes=2 << 30) as tree:
+        insert_batches(tree, to_device(p), parts)
+        assert_trees_equal(canonical(tree), ref, f"parts {parts}")
+
+
+def test_host_input_and_auto_split_match_device_input():
+    import pointgen
+
+    p = pointgen.tiny_planes(200_000, seed=5)
+    cfg = LodConfig(leaf_capacity=3_000, grid_bits=6, max_depth=12, chunk_capacity=500)
+    ref = O1.build(p, cfg)
+    log("case: host pointer input, max_batch 30000")
+    with make_octree(cfg, max_batch=30_000) as tree:
+        tree.insert(p[:123_457])  # numpy host memory, cut into passes of 30k
+        tree.insert(p[123_457:])
+        assert tree.stats()["batches"] == 5 + 3
+        assert_trees_equal(canonical(tree), ref, "host input")
+
+
+def test_identical_points_reach_max_depth_on_gpu():
+    cfg = LodConfig(leaf_capacity=10, grid_bits=7, max_depth=16, chunk_capacity=8)
+    n = 5_000
+    p = _pts(np.tile([[0.3, 0.6, 0.9]], (n, 1)), np.arange(n, dtype=np.uint32))
+    log("case: identical points")
+    with make_octree(cfg) as tree:
+        tree.insert(to_device(p[:7]))
+        tree.insert(to_device(p[7:]))
+        got = canonical(tree)
+        st = tree.stats()
+    assert_trees_equal(got, O1.build(p, cfg))
+    assert len(got.nodes) == 1 + 8 * 16 and got.num_voxels == 16
+    assert st["max_rounds"] == 17
+
+
+def test_empty_and_single_point_batches():
+    cfg = LodConfig(leaf_capacity=2, grid_bits=2, max_depth=4, chunk_capacity=2)
+    rng = np.random.default_rng(12)
+    p = _tiny(rng, 40)
+    log("case: empty and single batches")
+    with make_octree(cfg) as tree:
+        tree.insert(to_device(p[:0]))
+        for i in range(len(p)):
+            tree.insert(to_device(p[i:i + 1]))
+            tree.insert(p[:0])
+        got = canonical(tree)
+    assert_trees_equal(got, O1.build(p, cfg))
+    check_invariants(got, p, cfg)
+
+
+def test_non_power_of_two_domain():
+    rng = np.random.default_rng(13)
+    cfg = LodConfig(root_min=(-12.7, 3.3, 100.1), root_size=37.9, leaf_capacity=50,
+                    grid_bits=4, max_depth=9, chunk_capacity=64)
+    xyz = np.array(cfg.root_min) + rng.random((60_000, 3)) ** 2 * 37.9
+    p = _pts(xyz, rng.integers(0, 2**32, len(xyz), dtype=np.uint32))
+    log("case: non-power-of-two domain")
+    with make_octree(cfg) as tree:
+        insert_batches(tree, to_device(p), [10_000, 20_000, 30_000])
+        assert_trees_equal(canonical(tree), O1.build(p, cfg))
+
+
+def test_reset_restarts_the_sequence():
+    rng = np.random.default_rng(14)
+    cfg = LodConfig(leaf_capacity=30, grid_bits=3, max_depth=8)
+    p = _tiny(rng, 2_000)
+    q = _tiny(rng, 1_500)
+    log("case: reset")
+    with make_octree(cfg) as tree:
+        tree.insert(to_device(p))
+        tree.reset()
+        tree.insert(to_device(q))
+        assert_trees_equal(canonical(tree), O1.build(q, cfg))
+        assert tree.stats()["points_inserted"] == 1_500
