@@ -312,9 +312,10 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
               dalloc(h, &t.spill_rec, cfg->spill_capacity) &&
               dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched[0], N) &&
               dalloc(h, &t.touched[1], N) && dalloc(h, &t.final_list, N) &&
-              dalloc(h, &t.vtouched, N) && dalloc(h, &t.active[0], work) &&
-              dalloc(h, &t.active[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
-              dalloc(h, &t.hval, h->hash_entries) && dalloc(h, &t.claims, cfg->backlog_capacity);
+              dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
+              dalloc(h, &t.amask[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
+              dalloc(h, &t.hval, h->hash_entries) &&
+              dalloc(h, &t.claims, cfg->backlog_capacity * kStripes);
     const u32 C = cfg->chunk_capacity;
     const u64 chunk_bytes = (u64)C * 20u + 4u;
     t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);

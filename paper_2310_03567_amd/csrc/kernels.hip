@@ -114,8 +114,10 @@ __device__ __forceinline__ bool wg_skip(const Counters* ctr, u32 round) {
 // ---------------------------------------------------------------- counting
 // Round 1 counts every batch point in its leaf (all leaves are open; a
 // leaf's counter adds to the points it already stores).  Round k >= 2 counts
-// only points whose leaf was created by round k-1's splits; round 2 walks all
-// of W, later rounds only the points counted in the round before.
+// only points whose leaf was created by round k-1's splits: round 2 walks all
+// of W, later rounds only the items marked in the previous round's mask.
+// Counts go to a per-workgroup LDS histogram first and reach the global
+// counters once per (workgroup, leaf).
 __global__ __launch_bounds__(256) void k_count(DevTree t, const uint4* batch, u32 n,
                                                u32 base_key, u32 round, u32 epoch) {
     __shared__ u32 lkey[kLds];
@@ -128,52 +130,33 @@ __global__ __launch_bounds__(256) void k_count(DevTree t, const uint4* batch, u3
     }
     __syncthreads();
 
-    u32 S = ctr->spill_count;
-    u32 nwork;
-    const u32* list = nullptr;
-    if (round == 1u) {
-        nwork = n;
-    } else if (round == 2u) {
-        nwork = S + n;
-    } else {
-        list = t.active[(round - 1u) & 1u];
-        nwork = min(ctr->active_count[(round - 1u) & 1u], t.active_cap);
-    }
-    u32* emit = round >= 2u ? t.active[round & 1u] : nullptr;
-    u32 open_epoch = epoch - 1u;
+    const u32 S = ctr->spill_count;
+    const u32 nwork = round == 1u ? n : S + n;
+    const uint8_t* prev = round >= 3u ? t.amask[(round - 1u) & 1u] : nullptr;
+    uint8_t* mark = round >= 2u ? t.amask[round & 1u] : nullptr;
+    const u32 open_epoch = epoch - 1u;
 
     const u32 step = gridDim.x * kWG;
     for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
-        u32 j = base + threadIdx.x;
-        bool valid = j < nwork;
-        u32 widx = 0u, leaf = kNone;
-        if (valid) {
-            widx = list ? list[j] : j;
+        const u32 j = base + threadIdx.x;
+        u32 leaf = kNone;
+        if (j < nwork && (!prev || prev[j])) {
             uint4 rec;
             u32 key, qx, qy, qz;
-            fetch_work(t, batch, S, base_key, widx, rec, key);
+            fetch_work(t, batch, S, base_key, j, rec, key);
             quantize3(t, rec, qx, qy, qz);
             leaf = find_leaf(t, qx, qy, qz);
             if (round > 1u && t.birth[leaf] != open_epoch) leaf = kNone;
         }
-        if (emit) {
-            bool e = leaf != kNone;
-            u32 pos = wave_append(&ctr->active_count[round & 1u], e);
-            if (e) {
-                if (pos < t.active_cap)
-                    emit[pos] = widx;
-                else
-                    set_status(t, SIMLOD_OVF_WORK);
-            }
-        }
-        Run r = lane_runs(leaf);
+        if (mark && j < nwork) mark[j] = leaf != kNone ? 1u : 0u;
+        const Run r = lane_runs(leaf);
         if (leaf != kNone && r.rank == 0u) {
             if (!count_lds(lkey, lval, leaf, r.len)) count_global(t, leaf, r.len, round);
         }
     }
     __syncthreads();
     for (u32 e = threadIdx.x; e < kLds; e += kWG) {
-        u32 node = lkey[e];
+        const u32 node = lkey[e];
         if (node != kNone) count_global(t, node, lval[e], round);
     }
 }
@@ -189,10 +172,7 @@ __global__ __launch_bounds__(256) void k_split(DevTree t, u32 round, u32 epoch) 
     __shared__ i32 s_pool;
     Counters* ctr = t.ctr;
     if (wg_skip(ctr, round)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr->touched_count[(round + 1u) & 1u] = 0u;
-        ctr->active_count[(round + 1u) & 1u] = 0u;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->touched_count[(round + 1u) & 1u] = 0u;
     u32 nt = min(ctr->touched_count[round & 1u], t.max_nodes);
     const u32* touched = t.touched[round & 1u];
     const u32 tid = threadIdx.x;
@@ -395,24 +375,66 @@ __device__ __forceinline__ bool claim_cell(const DevTree& t, u64 tag, u64 val, u
 }
 
 // ------------------------------------------------------- sample and store
+// LDS tables of one workgroup (open addressing on u32 node ids).  The tables
+// are sized above the number of distinct keys a workgroup can insert, except
+// where a caller falls back to a global atomic when a table is full.
+__device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key) {
+    const u32 size = 1u << bits;
+    u32 h = (key * 0x9E3779B1u) >> (32u - bits);
+    for (u32 p = 0; p < size; ++p) {
+        const u32 k = atomicCAS(&keys[h], kNone, key);
+        if (k == kNone || k == key) return h;
+        h = (h + 1u) & (size - 1u);
+    }
+    return kNone;
+}
+
+constexpr u32 kClaimBuf = 2048;  // claims staged per workgroup before one flush
+constexpr u32 kSlotBits = 9;     // > 256 distinct leaves per tile
+constexpr u32 kNodeBits = 8;     // inner nodes with new voxels per workgroup
+
 // Walks each point of W once more from the root.  At every inner node it
 // projects the point into the node's R^3 grid (cell = (q >> (Dmax - d)) &
 // (R - 1) per axis); a cell whose bit is still clear from earlier passes is
 // claimed in the claim table with the point's key, the smallest key winning.
 // Consecutive lanes that hit the same cell with increasing keys claim once.
-// At the leaf the point takes the next slot of the leaf (run-aggregated
-// atomics on count) and is written, with its key, into the chunk slot/C.
+// At the leaf the point takes the next slot of the leaf and is written, with
+// its key, into the chunk slot / C.
+//
+// Same-address device atomics serialize (about 11 ns each on MI355X), so
+// nothing here issues one per wave on a shared counter: leaf slots are
+// reserved per (workgroup, leaf) after an LDS histogram of the tile, per-node
+// voxel counts are summed in LDS and flushed once per workgroup, and claimed
+// cells are staged in LDS and appended with one atomic per workgroup on one
+// of kStripes counters (workgroup id mod kStripes, i.e. one per XCD).
 __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* batch, u32 n,
                                                       u32 base_key) {
+    __shared__ u32 s_claims[kClaimBuf];
+    __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
+    __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
+    __shared__ u32 s_nclaims, s_flush;
     Counters* ctr = t.ctr;
-    if (__builtin_amdgcn_readfirstlane(ctr->status)) return;  // wave-uniform
+    if (wg_skip(ctr, 1u)) return;
+    const u32 tid = threadIdx.x;
+    for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
+        s_lkey[i] = kNone;
+        s_lcnt[i] = 0u;
+    }
+    for (u32 i = tid; i < (1u << kNodeBits); i += kWG) {
+        s_vkey[i] = kNone;
+        s_vcnt[i] = 0u;
+    }
+    if (tid == 0) s_nclaims = 0u;
+    __syncthreads();
+
     const u32 S = ctr->spill_count;
     const u32 nwork = S + n;
     const u32 lane = lane_id();
     const u32 rmask = t.R - 1u;
+    const u32 stripe = blockIdx.x % kStripes;
     const u32 step = gridDim.x * kWG;
     for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
-        const u32 j = base + threadIdx.x;
+        const u32 j = base + tid;
         const bool valid = j < nwork;
         uint4 rec = make_uint4(0u, 0u, 0u, 0u);
         u32 key = 0u, qx = 0u, qy = 0u, qz = 0u;
@@ -440,18 +462,33 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             bool fresh = false;
             u32 hslot = 0u;
             if (cand) fresh = claim_cell(t, tag, ((u64)key << 32) | (u64)rec.w, hslot);
-            const u32 pos = wave_append(&ctr->claim_count, fresh);
-            if (fresh) {
-                if (pos < t.claim_cap)
-                    t.claims[pos] = hslot;
-                else
-                    set_status(t, SIMLOD_OVF_BACKLOG);
+            // stage the claim in LDS (one LDS atomic per wave)
+            const u64 fm = __ballot(fresh);
+            if (fm) {
+                const int leader = __ffsll((long long)fm) - 1;
+                u32 off = 0u;
+                if ((int)lane == leader) off = atomicAdd(&s_nclaims, (u32)__popcll(fm));
+                off = __shfl(off, leader) + (u32)__popcll(fm & lanes_below(lane));
+                if (fresh) {
+                    if (off < kClaimBuf) {
+                        s_claims[off] = hslot;
+                    } else {  // staging full: append straight to the stripe
+                        const u32 pos = atomicAdd(&ctr->claim_count[stripe], 1u);
+                        if (pos < t.claim_cap)
+                            t.claims[(u64)stripe * t.claim_cap + pos] = hslot;
+                        else
+                            set_status(t, SIMLOD_OVF_BACKLOG);
+                    }
+                }
             }
+            // count new voxels per node in LDS
             const Run vr = lane_runs(fresh ? node : kNone);
             if (fresh && vr.rank == 0u) {
-                u32 old = atomicAdd(&t.newv[node], vr.len);
-                if (old == 0u) {
-                    u32 p = atomicAdd(&ctr->vtouched_count, 1u);
+                const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
+                if (e != kNone) {
+                    atomicAdd(&s_vcnt[e], vr.len);
+                } else if (atomicAdd(&t.newv[node], vr.len) == 0u) {
+                    const u32 p = atomicAdd(&ctr->vtouched_count, 1u);
                     if (p < t.max_nodes)
                         t.vtouched[p] = node;
                     else
@@ -463,13 +500,24 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             else
                 desc = false;
         }
+        // leaf slots: LDS histogram of the tile, one global atomic per leaf
         const u32 leaf = valid ? node : kNone;
         const Run r = lane_runs(leaf);
-        u32 sb = 0u;
-        if (valid && r.rank == 0u) sb = atomicAdd(&t.count[leaf], r.len);
-        sb = __shfl(sb, r.head);
+        u32 e = kNone, r0 = 0u;
+        if (leaf != kNone && r.rank == 0u) {
+            e = lds_find_or_insert(s_lkey, kSlotBits, leaf);  // never full: <= 256 keys
+            r0 = atomicAdd(&s_lcnt[e], r.len);
+        }
+        e = __shfl(e, r.head);
+        r0 = __shfl(r0, r.head) + r.rank;
+        __syncthreads();
+        for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
+            const u32 k = s_lkey[i];
+            if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
+        }
+        __syncthreads();
         if (valid) {
-            const u32 slot = sb + r.rank;
+            const u32 slot = s_lbase[e] + r0;
             const u32 ci = slot / t.C;
             if (ci < t.nchunks[leaf]) {
                 const u32 cb = table_of(t, leaf)[ci];
@@ -479,6 +527,34 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             } else {
                 set_status(t, SIMLOD_OVF_ARENA);
             }
+        }
+        __syncthreads();
+        for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
+            s_lkey[i] = kNone;
+            s_lcnt[i] = 0u;
+        }
+        __syncthreads();
+    }
+    // flush staged claims (one atomic per workgroup) and per-node counts
+    const u32 nc = min(s_nclaims, kClaimBuf);
+    if (tid == 0) s_flush = nc ? atomicAdd(&ctr->claim_count[stripe], nc) : 0u;
+    __syncthreads();
+    u32* dst = t.claims + (u64)stripe * t.claim_cap;
+    for (u32 i = tid; i < nc; i += kWG) {
+        const u32 pos = s_flush + i;
+        if (pos < t.claim_cap)
+            dst[pos] = s_claims[i];
+        else
+            set_status(t, SIMLOD_OVF_BACKLOG);
+    }
+    for (u32 i = tid; i < (1u << kNodeBits); i += kWG) {
+        const u32 node = s_vkey[i];
+        if (node != kNone && atomicAdd(&t.newv[node], s_vcnt[i]) == 0u) {
+            const u32 p = atomicAdd(&ctr->vtouched_count, 1u);
+            if (p < t.max_nodes)
+                t.vtouched[p] = node;
+            else
+                set_status(t, SIMLOD_OVF_WORK);
         }
     }
 }
@@ -490,7 +566,10 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
 __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
     Counters* ctr = t.ctr;
     if (__builtin_amdgcn_readfirstlane(ctr->status)) return;  // wave-uniform
-    const u32 n = min(ctr->claim_count, t.claim_cap);
+    u32 pre[kStripes + 1];
+    pre[0] = 0u;
+    for (u32 s = 0; s < kStripes; ++s) pre[s + 1] = pre[s] + min(ctr->claim_count[s], t.claim_cap);
+    const u32 n = pre[kStripes];
     const u32 rmask = t.R - 1u;
     const u32 step = gridDim.x * kWG;
     for (u32 base = blockIdx.x * kWG; base < n; base += step) {
@@ -499,7 +578,9 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
         u32 h = 0u, node = kNone, lin = 0u;
         u64 val = 0ull;
         if (valid) {
-            h = t.claims[i];
+            u32 s = 0;
+            while (i >= pre[s + 1]) ++s;
+            h = t.claims[(u64)s * t.claim_cap + (i - pre[s])];
             const u64 tag = t.htag[h];
             val = t.hval[h];
             node = (u32)(tag >> 24);
@@ -545,21 +626,22 @@ __global__ void k_finish(DevTree t) {
     u32 rounds = 1u;
     for (u32 k = 1; k <= (u32)kMaxRounds; ++k)
         if (c->split_any[k]) rounds = k + 1u;
+    u32 claims = 0u;
+    for (u32 k = 0; k < kStripes; ++k) claims += min(c->claim_count[k], t.claim_cap);
     c->last_rounds = rounds;
     c->last_spilled = c->spill_count;
-    c->last_new_voxels = c->claim_count;
+    c->last_new_voxels = claims;
     c->max_rounds = max(c->max_rounds, rounds);
     c->max_spilled = max(c->max_spilled, c->spill_count);
-    c->max_new_voxels = max(c->max_new_voxels, c->claim_count);
+    c->max_new_voxels = max(c->max_new_voxels, claims);
     c->sum_spilled += c->spill_count;
-    c->sum_new_voxels += c->claim_count;
+    c->sum_new_voxels += claims;
     c->sum_rounds += rounds;
     c->spill_count = 0u;
     c->final_count = 0u;
     c->vtouched_count = 0u;
-    c->claim_count = 0u;
+    for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
     c->touched_count[0] = c->touched_count[1] = 0u;
-    c->active_count[0] = c->active_count[1] = 0u;
     for (u32 k = 0; k < (u32)kMaxRounds + 2u; ++k) c->split_any[k] = 0u;
 }
 

@@ -43,6 +43,7 @@ constexpr u32 kNone = 0xFFFFFFFFu;
 constexpr u64 kEmptyTag = ~0ull;
 constexpr u32 kBlockBytes = 256;
 constexpr int kMaxRounds = 24;  // >= max_depth + 1
+constexpr u32 kStripes = 8;     // claim-list stripes (one per XCD)
 
 // Device-resident counters of one octree.
 struct Counters {
@@ -53,9 +54,8 @@ struct Counters {
     u32 spill_count;     // points moved to the spill buffer this pass
     u32 final_count;     // leaves finalized this pass
     u32 vtouched_count;  // inner nodes that claimed voxels this pass
-    u32 claim_count;     // voxels claimed this pass (backlog length)
+    u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
     u32 touched_count[2];
-    u32 active_count[2];
     u32 split_any[kMaxRounds + 2];
     // statistics of the last pass and high-water marks
     u32 last_rounds, last_spilled, last_new_voxels;
@@ -89,12 +89,12 @@ struct DevTree {
     u32* touched[2];
     uint2* final_list;   // {leaf, points added}
     u32* vtouched;       // inner nodes with new voxels
-    u32* active[2];      // work-list indices still being counted
+    uint8_t* amask[2];   // per work item: counted in the previous round
     u32 active_cap;
     u64* htag;           // voxel claim table: (node << 24 | cell) or empty
     u64* hval;           // (key << 32 | rgba), min-reduced
     u32 hmask;
-    u32* claims;         // claim-table slots of the voxels claimed this pass
+    u32* claims;         // claim-table slots claimed this pass, kStripes x claim_cap
     u32 claim_cap;
     // geometry and parameters
     float mn[3];
