@@ -70,6 +70,8 @@ extern "C" {
 #define SIMLOD_OVF_BACKLOG 0x8u /* voxel backlog (backlog_capacity) full   */
 #define SIMLOD_OVF_WORK 0x10u   /* expansion work list full                */
 #define SIMLOD_OVF_HASH 0x20u   /* voxel claim table probe limit reached   */
+#define SIMLOD_OVF_INTERNAL 0x40u /* internal consistency check failed     */
+#define SIMLOD_OVF_HIST 0x80u   /* split histograms (hist_capacity) full    */
 
 /* ---- records ---------------------------------------------------------- */
 
@@ -104,6 +106,9 @@ typedef struct simlod_point {
  * chunk_capacity       C: records per chunk (section "Chunks and the Chunk
  *                      Pool": 1000).  Changes layout only, never results.
  * max_nodes            Node table capacity (>= 9).
+ * hist_capacity        Leaves that may be mid-split at once in one pass: each
+ *                      takes a histogram of 4,680 counters (18.7 KB) of the
+ *                      points below it, 4 levels deep; 0 = 8192.
  * arena_bytes          Persistent buffer for chunks, occupancy grids and
  *                      chunk tables; 0 = 90% of the free device memory left
  *                      after the other buffers (section "Persistent Buffer").
@@ -124,7 +129,7 @@ typedef struct simlod_config {
     uint32_t max_depth;
     uint32_t chunk_capacity;
     uint32_t max_nodes;
-    uint32_t reserved0;
+    uint32_t hist_capacity;
     uint64_t arena_bytes;
     uint64_t max_batch;
     uint64_t spill_capacity;
@@ -199,7 +204,8 @@ typedef struct simlod_octree simlod_octree; /* opaque handle */
 
 /* Fills *cfg with the paper's parameters (T = 50,000, 128^3 grid, chunks of
  * 1,000, section "Octree") and default capacities: unit cube at the origin,
- * max_depth 16, 2^20 nodes, arena 0 (= 90% of free memory), max_batch 10M,
+ * max_depth 16, 2^20 nodes, 8192 split histograms, arena 0 (= 90% of free
+ * memory), max_batch 10M,
  * spill 16M, backlog 10M (section "Voxel Sampling"), device 0. */
 int simlod_default_config(simlod_config* cfg);
 

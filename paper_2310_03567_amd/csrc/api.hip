@@ -104,6 +104,7 @@ bool cfg_valid(const simlod_config* c) {
     if (c->spill_capacity > 0xFFFFFFFFull || c->max_batch + c->spill_capacity > 0xFFFFFFFFull)
         return false;
     if (c->backlog_capacity < 1 || c->backlog_capacity > (1ull << 31)) return false;
+    if (c->hist_capacity > (1u << 31) / kHistEntries) return false;
     return true;
 }
 
@@ -195,16 +196,16 @@ bool is_device_ptr(const void* p) {
 // One insertion pass over n <= max_batch device-resident points.
 hipError_t enqueue_pass(simlod_octree* h, const uint4* batch, u32 n, u32 base_key, hipStream_t s) {
     const DevTree& t = h->t;
-    const u32 rounds = h->cfg.max_depth + 1u;
-    const u32 e0 = h->epoch;
-    hipError_t e = hipSuccess;
-    for (u32 k = 1; k <= rounds && e == hipSuccess; ++k) {
+    const u32 rounds = expansion_rounds(h->cfg.max_depth);
+    hipError_t e = timed(h, SIMLOD_KERNEL_COUNT, s, [&] { return launch_count_leaves(t, batch, n, s); });
+    if (e == hipSuccess)
+        e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(t, n, s); });
+    for (u32 k = 2; k <= rounds && e == hipSuccess; ++k) {
         e = timed(h, SIMLOD_KERNEL_COUNT, s,
-                  [&] { return launch_count(t, batch, n, base_key, k, e0 + k, s); });
-        if (e != hipSuccess) break;
-        e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split(t, k, e0 + k, n, s); });
+                  [&] { return launch_count_hist(t, batch, n, base_key, k, s); });
+        if (e == hipSuccess)
+            e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_build(t, k, s); });
     }
-    h->epoch += rounds + 1u;
     if (e == hipSuccess)
         e = timed(h, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(t, 0u, s); });
     if (e == hipSuccess)
@@ -275,6 +276,7 @@ int simlod_default_config(simlod_config* cfg) {
     cfg->max_depth = 16;
     cfg->chunk_capacity = 1000;
     cfg->max_nodes = 1u << 20;
+    cfg->hist_capacity = 8192;
     cfg->arena_bytes = 0;
     cfg->max_batch = 10000000ull;
     cfg->spill_capacity = 16000000ull;
@@ -305,13 +307,18 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     const u64 N = cfg->max_nodes;
     const u64 work = cfg->max_batch + cfg->spill_capacity;
     h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
+    t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
+    const u32 hist_slots = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
     bool ok = dalloc(h, &t.child, N) && dalloc(h, &t.count, N) && dalloc(h, &t.cnt, N) &&
-              dalloc(h, &t.birth, N) && dalloc(h, &t.geo, N) && dalloc(h, &t.grid, N) &&
+              dalloc(h, &t.hslot, N) && dalloc(h, &t.geo, N) && dalloc(h, &t.grid, N) &&
               dalloc(h, &t.tab, N) && dalloc(h, &t.tabcap, N) && dalloc(h, &t.nchunks, N) &&
               dalloc(h, &t.newv, N) && dalloc(h, &t.ctr, 1) &&
+              dalloc(h, &t.dir, dir_offset(t.dir_depth + 1u)) &&
               dalloc(h, &t.spill_rec, cfg->spill_capacity) &&
-              dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched[0], N) &&
-              dalloc(h, &t.touched[1], N) && dalloc(h, &t.final_list, N) &&
+              dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched, N) &&
+              dalloc(h, &t.pending[0], N) && dalloc(h, &t.pending[1], N) &&
+              dalloc(h, &t.zero_list, N) &&
+              dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
               dalloc(h, &t.amask[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
               dalloc(h, &t.hval, h->hash_entries) &&
@@ -347,6 +354,7 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     }
     *h->h_status = 0;
     t.max_nodes = cfg->max_nodes;
+    t.hist_cap = hist_slots;
     t.spill_cap = (u32)cfg->spill_capacity;
     t.active_cap = (u32)work;
     t.hmask = (u32)(h->hash_entries - 1);

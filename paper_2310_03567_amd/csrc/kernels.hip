@@ -1,11 +1,19 @@
 // gfx950 kernels of one insertion pass (section "Incrementally Updating the
 // Octree").  A pass over a batch of n points runs, on one stream:
 //
-//   k_count / k_split, round k = 1..Dmax+1   expansion (subsection
-//       "Expanding the Octree"); rounds after the first that finds no leaf
-//       to split exit at once on a device flag, so the host never waits
+//   k_count_leaves, k_split_leaves   first expansion round: count the batch
+//       per leaf; a leaf whose stored plus new points exceed T (above Dmax)
+//       becomes a pending root: its stored points move to the spill buffer
+//       and it gets a histogram slot (subsection "Expanding the Octree")
+//   k_count_hist, k_build, rounds 2..R
+//       every point in a pending root adds to the root's histogram of its
+//       descendants kHistLevels levels down; the build kernel then creates
+//       that whole part of the subtree at once, and descendants at the
+//       histogram's last level that still hold more than T points become the
+//       next round's pending roots.  R = 1 + ceil(Dmax / kHistLevels) rounds
+//       always suffice; rounds without pending roots exit at once.
 //   k_alloc(points)      chunks for the leaves' new points (subsection
-//                        "Allocating Chunks")
+//                        "Allocating Chunks"), and clearing of new grids
 //   k_sample_store       one traversal per point: voxel claims at every
 //                        inner node on the path (subsection "Voxel Sampling")
 //                        and the point's store into its leaf (subsection
@@ -14,12 +22,19 @@
 //   k_store_voxels       voxel records from the claim backlog
 //   k_finish             per-pass bookkeeping
 //
+// The paper repeats count/split one level at a time; counting several levels
+// per round gives the same octree (a node is inner iff its region holds more
+// than T points, whatever order the levels are decided in) with far fewer
+// passes over the batch and kernel launches.
+//
 // The work list W of a pass is the spill buffer followed by the batch:
 // index i < S names spilled point i (with the key it was stored with),
 // index i >= S names batch point i - S with key base_key + i - S.
 //
 // All cross-workgroup communication inside one kernel goes through atomics;
-// anything else written in one kernel is read in a later one.
+// anything else written in one kernel is read in a later one.  Same-address
+// device atomics serialize (about 11 ns each on MI355X), so counters that
+// many workgroups update are aggregated in LDS first.
 #include "octree_device.hpp"
 #include "simlod.h"
 #include "launch.hpp"
@@ -30,6 +45,7 @@ constexpr u32 kWG = 256;
 constexpr u32 kLdsBits = 11;
 constexpr u32 kLds = 1u << kLdsBits;
 constexpr u32 kMaxProbe = 4096;
+constexpr u32 kHistKey = 0x80000000u;  // LDS key flag: a histogram counter
 
 // Renumbers workgroups so that each of the 8 XCDs (which receive workgroups
 // round-robin) walks a contiguous range of tiles: neighbouring points, and
@@ -58,190 +74,186 @@ __device__ __forceinline__ void quantize3(const DevTree& t, const uint4& rec, u3
     qz = quantize(__uint_as_float(rec.z), t.mn[2], t.scale, t.K);
 }
 
+__device__ __forceinline__ u32 cell_lin(u32 qx, u32 qy, u32 qz, u32 shift, u32 r, u32 rmask) {
+    return ((qx >> shift) & rmask) | (((qy >> shift) & rmask) << r) |
+           (((qz >> shift) & rmask) << (2u * r));
+}
+
 // Root-to-leaf walk: the child of a node at depth d takes bit K-1-d of each
-// integer coordinate (x bit 0, y bit 1, z bit 2 of the octant).
-__device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 qz) {
-    u32 node = 0;
-    u32 bit = t.K - 1u;
-    u32 c = t.child[0];
-    for (u32 d = 0; c != 0u && d < t.Dmax; ++d) {  // children exist only above Dmax
+// integer coordinate (x bit 0, y bit 1, z bit 2 of the octant).  Depths up to
+// dir_depth come from the node directory in one round of independent loads;
+// the walk continues through child[] below that.  Returns the leaf and sets
+// its depth.
+__device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 qz, u32& depth) {
+    const u32 D = t.dir_depth;
+    const u32 m = dir_index(t.K, D, qx, qy, qz);
+    u32 e[kDirMaxDepth + 1];
+#pragma unroll
+    for (u32 d = 0; d <= kDirMaxDepth; ++d)
+        e[d] = d <= D ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
+#pragma unroll
+    for (u32 d = 0; d <= kDirMaxDepth; ++d) {
+        if (d <= D && !(e[d] & kDirInner)) {  // a leaf at depth d
+            depth = d;
+            return e[d];
+        }
+        if (d <= D && e[d] == kNone) {  // inconsistent directory
+            set_status(t, SIMLOD_OVF_INTERNAL);
+            depth = 0;
+            return 0u;
+        }
+    }
+    u32 node = e[D] & ~kDirInner;  // inner at every directory depth
+    u32 bit = t.K - 1u - D;
+    u32 c = t.child[node];
+    u32 d = D;
+    for (; c != 0u && d < t.Dmax; ++d) {  // children exist only above Dmax
         node = c + octant_of(qx, qy, qz, bit);
         --bit;
         c = t.child[node];
     }
+    depth = d;
     return node;
 }
 
-// Adds c to a leaf's round counter; the first addition of the round lists
-// the leaf for the split kernel.
-__device__ __forceinline__ void count_global(const DevTree& t, u32 node, u32 c, u32 round) {
-    u32 old = atomicAdd(&t.cnt[node], c);
-    if (old == 0u) {
-        u32 p = atomicAdd(&t.ctr->touched_count[round & 1u], 1u);
+// Workgroup-uniform early exit.  skip_if_zero (may be null): also exit when
+// that counter is zero.  The status word can change while a kernel runs, so
+// one thread reads and the decision is broadcast through LDS before any
+// barrier is reached.
+__device__ __forceinline__ bool wg_skip(const Counters* ctr, const u32* skip_if_zero) {
+    __shared__ u32 s_skip;
+    if (threadIdx.x == 0)
+        s_skip = (ctr->status != 0u || (skip_if_zero && *skip_if_zero == 0u)) ? 1u : 0u;
+    __syncthreads();
+    return s_skip != 0u;
+}
+
+// ------------------------------------------------------ LDS aggregation
+// Open-addressing table on u32 keys; returns the entry or kNone when full.
+__device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key) {
+    const u32 size = 1u << bits;
+    u32 h = (key * 0x9E3779B1u) >> (32u - bits);
+    for (u32 p = 0; p < size; ++p) {
+        const u32 k = atomicCAS(&keys[h], kNone, key);
+        if (k == kNone || k == key) return h;
+        h = (h + 1u) & (size - 1u);
+    }
+    return kNone;
+}
+
+// Adds c to a leaf's first-round counter; the first addition lists the leaf.
+__device__ __forceinline__ void count_leaf_global(const DevTree& t, u32 node, u32 c) {
+    if (atomicAdd(&t.cnt[node], c) == 0u) {
+        const u32 p = atomicAdd(&t.ctr->touched_count, 1u);
         if (p < t.max_nodes)
-            t.touched[round & 1u][p] = node;
+            t.touched[p] = node;
         else
             set_status(t, SIMLOD_OVF_WORK);
     }
 }
 
-// Per-workgroup histogram in LDS (open addressing); false when full.
-__device__ __forceinline__ bool count_lds(u32* lkey, u32* lval, u32 node, u32 c) {
-    u32 h = (node * 0x9E3779B1u) >> (32u - kLdsBits);
-    for (u32 p = 0; p < 32u; ++p) {
-        u32 k = atomicCAS(&lkey[h], kNone, node);
-        if (k == kNone || k == node) {
-            atomicAdd(&lval[h], c);
-            return true;
-        }
-        h = (h + 1u) & (kLds - 1u);
-    }
-    return false;
+// Flushes one LDS-aggregated count: a leaf counter or a histogram counter.
+__device__ __forceinline__ void flush_count(const DevTree& t, u32 key, u32 c) {
+    if (key & kHistKey)
+        atomicAdd(&t.hist[key & ~kHistKey], c);
+    else
+        count_leaf_global(t, key, c);
 }
 
-// Workgroup-uniform early exit: the handle is poisoned, or the previous
-// round split nothing.  The status word can change while the kernel runs, so
-// one thread reads it and the decision is broadcast through LDS before any
-// barrier is reached.
-__device__ __forceinline__ bool wg_skip(const Counters* ctr, u32 round) {
-    __shared__ u32 s_skip;
-    if (threadIdx.x == 0)
-        s_skip = (ctr->status != 0u || (round > 1u && ctr->split_any[round - 1u] == 0u)) ? 1u : 0u;
-    __syncthreads();
-    return s_skip != 0u;
-}
-
-// ---------------------------------------------------------------- counting
-// Round 1 counts every batch point in its leaf (all leaves are open; a
-// leaf's counter adds to the points it already stores).  Round k >= 2 counts
-// only points whose leaf was created by round k-1's splits: round 2 walks all
-// of W, later rounds only the items marked in the previous round's mask.
-// Counts go to a per-workgroup LDS histogram first and reach the global
-// counters once per (workgroup, leaf).
-__global__ __launch_bounds__(256) void k_count(DevTree t, const uint4* batch, u32 n,
-                                               u32 base_key, u32 round, u32 epoch) {
+// ---------------------------------------------------------- first round
+// Counts every batch point in its leaf.  All leaves are open in this round;
+// a leaf's total is its stored points plus this counter.
+__global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* batch, u32 n) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     Counters* ctr = t.ctr;
-    if (wg_skip(ctr, round)) return;
+    if (wg_skip(ctr, nullptr)) return;
     for (u32 i = threadIdx.x; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
     }
     __syncthreads();
-
-    const u32 S = ctr->spill_count;
-    const u32 nwork = round == 1u ? n : S + n;
-    const uint8_t* prev = round >= 3u ? t.amask[(round - 1u) & 1u] : nullptr;
-    uint8_t* mark = round >= 2u ? t.amask[round & 1u] : nullptr;
-    const u32 open_epoch = epoch - 1u;
-
     const u32 step = gridDim.x * kWG;
-    for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
+    for (u32 base = xcd_block() * kWG; base < n; base += step) {
         const u32 j = base + threadIdx.x;
         u32 leaf = kNone;
-        if (j < nwork && (!prev || prev[j])) {
-            uint4 rec;
-            u32 key, qx, qy, qz;
-            fetch_work(t, batch, S, base_key, j, rec, key);
-            quantize3(t, rec, qx, qy, qz);
-            leaf = find_leaf(t, qx, qy, qz);
-            if (round > 1u && t.birth[leaf] != open_epoch) leaf = kNone;
+        if (j < n) {
+            u32 qx, qy, qz, depth;
+            quantize3(t, batch[j], qx, qy, qz);
+            leaf = find_leaf(t, qx, qy, qz, depth);
         }
-        if (mark && j < nwork) mark[j] = leaf != kNone ? 1u : 0u;
         const Run r = lane_runs(leaf);
         if (leaf != kNone && r.rank == 0u) {
-            if (!count_lds(lkey, lval, leaf, r.len)) count_global(t, leaf, r.len, round);
+            const u32 e = lds_find_or_insert(lkey, kLdsBits, leaf);
+            if (e != kNone)
+                atomicAdd(&lval[e], r.len);
+            else
+                count_leaf_global(t, leaf, r.len);
         }
     }
     __syncthreads();
-    for (u32 e = threadIdx.x; e < kLds; e += kWG) {
-        const u32 node = lkey[e];
-        if (node != kNone) count_global(t, node, lval[e], round);
-    }
+    for (u32 e = threadIdx.x; e < kLds; e += kWG)
+        if (lkey[e] != kNone) count_leaf_global(t, lkey[e], lval[e]);
 }
 
-// ---------------------------------------------------------------- splitting
-// One workgroup per leaf counted this round.  A leaf whose stored plus
-// counted points exceed T (and that is above Dmax) becomes inner: 8 empty
-// children, a zeroed occupancy grid, its stored points and keys appended to
-// the spill buffer and its chunks pushed to the pool.  Any other counted leaf
-// is final for the pass and listed with its number of new points.
-__global__ __launch_bounds__(256) void k_split(DevTree t, u32 round, u32 epoch) {
-    __shared__ u32 s_dec[4];
+// One workgroup per leaf counted in the first round.  A leaf whose stored
+// plus counted points exceed T (and that is above Dmax) becomes a pending
+// root: a zeroed histogram slot, its stored points and keys appended to the
+// spill buffer (they are re-inserted with the batch) and its chunks pushed to
+// the pool (section "Chunks and the Chunk Pool").  Any other counted leaf is
+// final for the pass and listed with its number of new points.
+__global__ __launch_bounds__(256) void k_split_leaves(DevTree t) {
+    __shared__ u32 s_dec[3];
     __shared__ i32 s_pool;
     Counters* ctr = t.ctr;
-    if (wg_skip(ctr, round)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->touched_count[(round + 1u) & 1u] = 0u;
-    u32 nt = min(ctr->touched_count[round & 1u], t.max_nodes);
-    const u32* touched = t.touched[round & 1u];
+    if (wg_skip(ctr, nullptr)) return;
+    const u32 nt = min(ctr->touched_count, t.max_nodes);
     const u32 tid = threadIdx.x;
     for (u32 it = blockIdx.x; it < nt; it += gridDim.x) {
-        u32 L = touched[it];
+        const u32 L = t.touched[it];
         if (tid == 0) {
-            u32 c = t.cnt[L];
-            u32 stored = t.count[L];
-            u32 depth = t.geo[L].w;
-            u32 split = 0u, first = 0u, gblk = 0u, sbase = 0u;
+            const u32 c = t.cnt[L];
+            const u32 stored = t.count[L];
+            const u32 depth = t.geo[L].w;
+            u32 pend = 0u, slot = 0u, sbase = 0u;
             if ((u64)stored + c > (u64)t.T && depth < t.Dmax) {
-                first = atomicAdd(&ctr->node_count, 8u);
-                if ((u64)first + 8u > (u64)t.max_nodes) {
-                    set_status(t, SIMLOD_OVF_NODES);
-                } else {
-                    gblk = atomicAdd(&ctr->arena_top, t.grid_blocks);
-                    if ((u64)gblk + t.grid_blocks > (u64)t.arena_blocks) {
-                        set_status(t, SIMLOD_OVF_ARENA);
-                    } else {
-                        sbase = stored ? atomicAdd(&ctr->spill_count, stored) : 0u;
-                        if ((u64)sbase + stored > (u64)t.spill_cap)
-                            set_status(t, SIMLOD_OVF_SPILL);
-                        else
-                            split = 1u;
-                    }
+                slot = atomicAdd(&ctr->hist_top, 1u);
+                const u32 p = atomicAdd(&ctr->pending_count[1], 1u);
+                sbase = stored ? atomicAdd(&ctr->spill_count, stored) : 0u;
+                if (slot >= t.hist_cap)
+                    set_status(t, SIMLOD_OVF_HIST);
+                else if (p >= t.max_nodes)
+                    set_status(t, SIMLOD_OVF_WORK);
+                else if ((u64)sbase + stored > (u64)t.spill_cap)
+                    set_status(t, SIMLOD_OVF_SPILL);
+                else {
+                    t.pending[1][p] = L;
+                    pend = 1u;
                 }
             } else {
-                u32 p = atomicAdd(&ctr->final_count, 1u);
+                const u32 p = atomicAdd(&ctr->final_count, 1u);
                 if (p < t.max_nodes)
                     t.final_list[p] = make_uint2(L, c);
                 else
                     set_status(t, SIMLOD_OVF_WORK);
-                t.cnt[L] = 0u;
             }
-            s_dec[0] = split;
-            s_dec[1] = first;
-            s_dec[2] = gblk;
-            s_dec[3] = sbase;
+            t.cnt[L] = 0u;
+            s_dec[0] = pend;
+            s_dec[1] = slot;
+            s_dec[2] = sbase;
         }
         __syncthreads();
         if (s_dec[0]) {
-            const u32 first = s_dec[1], gblk = s_dec[2], sbase = s_dec[3];
-            const uint4 g = t.geo[L];
-            const u32 depth = g.w;
-            const u32 bit = t.K - 1u - depth;
-            if (tid < 8u) {
-                u32 nd = first + tid;
-                t.child[nd] = 0u;
-                t.count[nd] = 0u;
-                t.cnt[nd] = 0u;
-                t.birth[nd] = epoch;
-                t.geo[nd] = make_uint4(g.x | ((tid & 1u) << bit), g.y | (((tid >> 1) & 1u) << bit),
-                                       g.z | (((tid >> 2) & 1u) << bit), depth + 1u);
-                t.grid[nd] = kNone;
-                t.tab[nd] = kNone;
-                t.tabcap[nd] = 0u;
-                t.nchunks[nd] = 0u;
-                t.newv[nd] = 0u;
-            }
-            uint4* gw = reinterpret_cast<uint4*>(block_ptr(t, gblk));
-            const u32 n16 = t.grid_blocks * (kBlockBytes / 16u);
-            for (u32 w = tid; w < n16; w += kWG) gw[w] = make_uint4(0u, 0u, 0u, 0u);
+            const u32 slot = s_dec[1], sbase = s_dec[2];
+            u32* h = t.hist + (u64)slot * kHistEntries;
+            for (u32 i = tid; i < kHistEntries; i += kWG) h[i] = 0u;
             const u32 stored = t.count[L];
             if (stored) {
                 const u32* tab = table_of(t, L);
                 for (u32 s = tid; s < stored; s += kWG) {
-                    u32 ci = s / t.C;
-                    u32 cb = tab[ci];
-                    u32 o = s - ci * t.C;
+                    const u32 ci = s / t.C;
+                    const u32 cb = tab[ci];
+                    const u32 o = s - ci * t.C;
                     t.spill_rec[sbase + s] = chunk_recs(t, cb)[o];
                     t.spill_key[sbase + s] = chunk_keys(t, cb)[o];
                 }
@@ -249,19 +261,286 @@ __global__ __launch_bounds__(256) void k_split(DevTree t, u32 round, u32 epoch) 
                 if (tid == 0) s_pool = atomicAdd(&ctr->pool_top, (i32)nch);
                 __syncthreads();
                 const i32 pb = s_pool;
-                for (u32 j = tid; j < nch; j += kWG) {
+                for (u32 j = tid; j < nch; j += kWG)
                     if ((u64)pb + j < (u64)t.pool_cap) t.pool[pb + j] = tab[j];
-                }
             }
             __syncthreads();
             if (tid == 0) {
                 t.count[L] = 0u;
                 t.nchunks[L] = 0u;
-                t.grid[L] = gblk;
-                t.cnt[L] = 0u;
-                t.child[L] = first;
-                ctr->split_any[round] = 1u;
+                t.hslot[L] = slot;
             }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------- histogram rounds
+// Relative Morton index, j levels below depth d, of integer position q.
+__device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u32 qz) {
+    const u32 s = K - d - j;
+    const u32 m = (1u << j) - 1u;
+    return spread3((qx >> s) & m) | (spread3((qy >> s) & m) << 1) | (spread3((qz >> s) & m) << 2);
+}
+
+// Round k >= 2: every point whose leaf is a pending root adds one to the
+// root's histogram at each of the kHistLevels levels below it (levels beyond
+// Dmax do not exist).  Round 2 walks all of W; later rounds only the items
+// counted in the round before.
+__global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batch, u32 n,
+                                                    u32 base_key, u32 round) {
+    __shared__ u32 lkey[kLds];
+    __shared__ u32 lval[kLds];
+    Counters* ctr = t.ctr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->pending_count[round & 1u] = 0u;
+    if (wg_skip(ctr, &ctr->pending_count[(round - 1u) & 1u])) return;
+    for (u32 i = threadIdx.x; i < kLds; i += kWG) {
+        lkey[i] = kNone;
+        lval[i] = 0u;
+    }
+    __syncthreads();
+    const u32 S = ctr->spill_count;
+    const u32 nwork = S + n;
+    const uint8_t* prev = round >= 3u ? t.amask[(round - 1u) & 1u] : nullptr;
+    uint8_t* mark = t.amask[round & 1u];
+    const u32 step = gridDim.x * kWG;
+    for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
+        const u32 j = base + threadIdx.x;
+        u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
+        if (j < nwork && (!prev || prev[j])) {
+            uint4 rec;
+            u32 key;
+            fetch_work(t, batch, S, base_key, j, rec, key);
+            quantize3(t, rec, qx, qy, qz);
+            const u32 leaf = find_leaf(t, qx, qy, qz, depth);
+            slot = t.hslot[leaf];
+        }
+        if (j < nwork) mark[j] = slot != kNone ? 1u : 0u;
+#pragma unroll
+        for (u32 lv = 1; lv <= kHistLevels; ++lv) {
+            u32 key = kNone;
+            if (slot != kNone && depth + lv <= t.Dmax)
+                key = kHistKey | (slot * kHistEntries + hist_level_offset(lv) +
+                                  rel_index(t.K, depth, lv, qx, qy, qz));
+            const Run r = lane_runs(key);
+            if (key != kNone && r.rank == 0u) {
+                const u32 e = lds_find_or_insert(lkey, kLdsBits, key);
+                if (e != kNone)
+                    atomicAdd(&lval[e], r.len);
+                else
+                    flush_count(t, key, r.len);
+            }
+        }
+    }
+    __syncthreads();
+    for (u32 e = threadIdx.x; e < kLds; e += kWG)
+        if (lkey[e] != kNone) flush_count(t, lkey[e], lval[e]);
+}
+
+// Exclusive prefix sum of a[0..n) in LDS by one workgroup; returns the total.
+// part: LDS scratch of kWG + 1 entries.
+__device__ u32 wg_exclusive_scan(u32* a, u32 n, u32* part) {
+    const u32 tid = threadIdx.x;
+    const u32 per = (n + kWG - 1u) / kWG;
+    const u32 lo = min(tid * per, n), hi = min(lo + per, n);
+    u32 sum = 0u;
+    for (u32 i = lo; i < hi; ++i) sum += a[i];
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        u32 run = 0u;
+        for (u32 i = 0; i < kWG; ++i) {
+            const u32 v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        part[kWG] = run;
+    }
+    __syncthreads();
+    u32 run = part[tid];
+    for (u32 i = lo; i < hi; ++i) {
+        const u32 v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return part[kWG];
+}
+
+// Index layout of one pending root's virtual subtree in the build kernel:
+// 0 = the root, 1 + hist_level_offset(j) + rel = the level-j descendant with
+// relative Morton path rel.  Only levels 0..kHistLevels-1 can split.
+constexpr u32 kTreeSlots = 1u + kHistEntries;
+constexpr u32 kSplitSlots = 1u + 8u + 64u + 512u;  // levels 0..kHistLevels-1
+constexpr u32 kFExists = 1u, kFSplit = 2u, kFPending = 4u, kFFinal = 8u;
+
+__device__ __forceinline__ void slot_level(u32 i, u32& lv, u32& rel) {
+    const u32 k = i - 1u;
+    lv = k < 8u ? 1u : (k < 72u ? 2u : (k < 584u ? 3u : 4u));
+    rel = k - hist_level_offset(lv);
+}
+
+__device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
+    return lv == 1u ? 0u : 1u + hist_level_offset(lv - 1u) + (rel >> 3);
+}
+
+// Round k >= 2: one workgroup per pending root X (depth d0).  From X's
+// histogram it decides the subtree kHistLevels levels down: a descendant at
+// level j < kHistLevels is inner iff it holds more than T points and is above
+// Dmax; one at the last level that must split becomes a pending root of the
+// next round (with a fresh histogram slot); every other descendant with
+// points is a final leaf listed with its point count.  X and its inner
+// descendants receive 8 consecutive children each (one node-count atomic per
+// root, in level order), occupancy grids (cleared later, in k_alloc) and
+// directory entries.
+__global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
+    __shared__ u32 s_h[kHistEntries];   // the root's histogram
+    __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
+    __shared__ u32 s_sp[kSplitSlots];   // split index of inner nodes
+    __shared__ u32 s_q[kTreeSlots];     // scan buffer
+    __shared__ u32 s_part[kWG + 1u];
+    __shared__ u32 s_alloc[8];
+    Counters* ctr = t.ctr;
+    const u32* in_count = &ctr->pending_count[(round - 1u) & 1u];
+    if (wg_skip(ctr, in_count)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr->build_rounds, 1u);
+    const u32 nroots = min(*in_count, t.max_nodes);
+    const u32* roots = t.pending[(round - 1u) & 1u];
+    const u32 out = round & 1u;
+    const u32 tid = threadIdx.x;
+    for (u32 it = blockIdx.x; it < nroots; it += gridDim.x) {
+        const u32 X = roots[it];
+        const uint4 gx = t.geo[X];
+        const u32 d0 = gx.w;
+        const u32* hsrc = t.hist + (u64)t.hslot[X] * kHistEntries;
+        for (u32 i = tid; i < kHistEntries; i += kWG) s_h[i] = hsrc[i];
+        if (tid == 0) s_f[0] = kFExists | kFSplit;
+        __syncthreads();
+        // flags, level by level (a level exists below the level above's splits)
+        for (u32 lv = 1; lv <= kHistLevels; ++lv) {
+            const u32 width = 1u << (3u * lv);
+            const u32 off = hist_level_offset(lv);
+            for (u32 rel = tid; rel < width; rel += kWG) {
+                u32 f = 0u;
+                if (s_f[slot_parent(lv, rel)] & kFSplit) {
+                    const u32 c = s_h[off + rel];
+                    f = kFExists;
+                    if (c > t.T && d0 + lv < t.Dmax)
+                        f |= lv < kHistLevels ? kFSplit : kFPending;
+                    else if (c > 0u)
+                        f |= kFFinal;
+                }
+                s_f[1u + off + rel] = f;
+            }
+            __syncthreads();
+        }
+        // split indices (level order) and per-kind counts
+        for (u32 i = tid; i < kSplitSlots; i += kWG) s_sp[i] = (s_f[i] & kFSplit) ? 1u : 0u;
+        __syncthreads();
+        const u32 nsplit = wg_exclusive_scan(s_sp, kSplitSlots, s_part);
+        for (u32 i = tid; i < kTreeSlots; i += kWG) s_q[i] = (s_f[i] & kFPending) ? 1u : 0u;
+        __syncthreads();
+        const u32 npend = wg_exclusive_scan(s_q, kTreeSlots, s_part);
+        if (tid == 0) {
+            u32 ok = 1u;
+            const u32 base = atomicAdd(&ctr->node_count, 8u * nsplit);
+            const u32 gbase = atomicAdd(&ctr->arena_top, nsplit * t.grid_blocks);
+            const u32 zbase = atomicAdd(&ctr->zero_count, nsplit);
+            const u32 hb = npend ? atomicAdd(&ctr->hist_top, npend) : 0u;
+            const u32 pb = npend ? atomicAdd(&ctr->pending_count[out], npend) : 0u;
+            if ((u64)base + 8ull * nsplit > (u64)t.max_nodes) {
+                set_status(t, SIMLOD_OVF_NODES);
+                ok = 0u;
+            } else if ((u64)gbase + (u64)nsplit * t.grid_blocks > (u64)t.arena_blocks) {
+                set_status(t, SIMLOD_OVF_ARENA);
+                ok = 0u;
+            } else if ((u64)zbase + nsplit > (u64)t.max_nodes ||
+                       (u64)pb + npend > (u64)t.max_nodes) {
+                set_status(t, SIMLOD_OVF_WORK);
+                ok = 0u;
+            } else if ((u64)hb + npend > (u64)t.hist_cap) {
+                set_status(t, SIMLOD_OVF_HIST);
+                ok = 0u;
+            }
+            s_alloc[0] = ok;
+            s_alloc[1] = base;
+            s_alloc[2] = gbase;
+            s_alloc[3] = zbase;
+            s_alloc[4] = hb;
+            s_alloc[5] = pb;
+        }
+        __syncthreads();
+        if (!s_alloc[0]) break;  // poisoned: later kernels do nothing
+        const u32 base = s_alloc[1], gbase = s_alloc[2], zbase = s_alloc[3];
+        const u32 hb = s_alloc[4], pb = s_alloc[5];
+        const u32 xidx = d0 <= t.dir_depth ? dir_index(t.K, d0, gx.x, gx.y, gx.z) : 0u;
+        // create every existing descendant (X itself already is a node)
+        for (u32 i = 1u + tid; i < kTreeSlots; i += kWG) {
+            const u32 f = s_f[i];
+            if (!(f & kFExists)) continue;
+            u32 lv, rel;
+            slot_level(i, lv, rel);
+            const u32 nd = base + 8u * s_sp[slot_parent(lv, rel)] + (rel & 7u);
+            const u32 depth = d0 + lv;
+            const u32 sh = t.K - depth;
+            t.count[nd] = 0u;
+            t.cnt[nd] = 0u;
+            t.geo[nd] = make_uint4(gx.x | (compact3(rel) << sh), gx.y | (compact3(rel >> 1) << sh),
+                                   gx.z | (compact3(rel >> 2) << sh), depth);
+            t.tab[nd] = kNone;
+            t.tabcap[nd] = 0u;
+            t.nchunks[nd] = 0u;
+            t.newv[nd] = 0u;
+            if (f & kFSplit) {
+                const u32 g = gbase + s_sp[i] * t.grid_blocks;
+                t.child[nd] = base + 8u * s_sp[i];
+                t.grid[nd] = g;
+                t.zero_list[zbase + s_sp[i]] = g;
+            } else {
+                t.child[nd] = 0u;
+                t.grid[nd] = kNone;
+            }
+            if (f & kFPending) {
+                t.hslot[nd] = hb + s_q[i];
+                t.pending[out][pb + s_q[i]] = nd;
+            } else {
+                t.hslot[nd] = kNone;
+            }
+            if (depth <= t.dir_depth)
+                t.dir[dir_offset(depth) + ((xidx << (3u * lv)) | rel)] =
+                    nd | ((f & kFSplit) ? kDirInner : 0u);
+        }
+        // the new pending roots' histograms start at zero
+        for (u64 i = tid; i < (u64)npend * kHistEntries; i += kWG)
+            t.hist[(u64)hb * kHistEntries + i] = 0u;
+        // the root becomes inner (split index 0)
+        if (tid == 0) {
+            t.grid[X] = gbase;
+            t.zero_list[zbase] = gbase;
+            t.hslot[X] = kNone;
+            t.child[X] = base;
+            if (d0 <= t.dir_depth) t.dir[dir_offset(d0) + xidx] = X | kDirInner;
+        }
+        __syncthreads();
+        // final leaves with their point counts
+        for (u32 i = tid; i < kTreeSlots; i += kWG) s_q[i] = (s_f[i] & kFFinal) ? 1u : 0u;
+        __syncthreads();
+        const u32 nfin = wg_exclusive_scan(s_q, kTreeSlots, s_part);
+        if (tid == 0) {
+            const u32 fb = nfin ? atomicAdd(&ctr->final_count, nfin) : 0u;
+            s_alloc[0] = (u64)fb + nfin <= (u64)t.max_nodes ? 1u : 0u;
+            if (!s_alloc[0]) set_status(t, SIMLOD_OVF_WORK);
+            s_alloc[6] = fb;
+        }
+        __syncthreads();
+        if (!s_alloc[0]) break;
+        const u32 fb = s_alloc[6];
+        for (u32 i = 1u + tid; i < kTreeSlots; i += kWG) {
+            if (!(s_f[i] & kFFinal)) continue;
+            u32 lv, rel;
+            slot_level(i, lv, rel);
+            const u32 nd = base + 8u * s_sp[slot_parent(lv, rel)] + (rel & 7u);
+            t.final_list[fb + s_q[i]] = make_uint2(nd, s_h[hist_level_offset(lv) + rel]);
         }
         __syncthreads();
     }
@@ -273,9 +552,21 @@ __global__ __launch_bounds__(256) void k_split(DevTree t, u32 round, u32 epoch) 
 // the pool first, then from the persistent buffer (section "Chunks and the
 // Chunk Pool"), are appended to the node's chunk table (grown by doubling)
 // and linked after its last chunk.
+// The first call of a pass (points) also clears the occupancy grids of the
+// pass's new inner nodes, spread over the whole grid.
 __global__ __launch_bounds__(256) void k_alloc(DevTree t, u32 voxels) {
     Counters* ctr = t.ctr;
     if (__builtin_amdgcn_readfirstlane(ctr->status)) return;  // wave-uniform
+    if (!voxels) {
+        const u32 nz = min(ctr->zero_count, t.max_nodes);
+        const u32 per = t.grid_blocks * (kBlockBytes / 16u);
+        const u64 total = (u64)nz * per;
+        for (u64 i = (u64)blockIdx.x * kWG + threadIdx.x; i < total; i += (u64)gridDim.x * kWG) {
+            const u32 z = (u32)(i / per);
+            reinterpret_cast<uint4*>(block_ptr(t, t.zero_list[z]))[i - (u64)z * per] =
+                make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
     u32 n = voxels ? ctr->vtouched_count : ctr->final_count;
     n = min(n, t.max_nodes);
     const u32 lane = lane_id();
@@ -375,23 +666,63 @@ __device__ __forceinline__ bool claim_cell(const DevTree& t, u64 tag, u64 val, u
 }
 
 // ------------------------------------------------------- sample and store
-// LDS tables of one workgroup (open addressing on u32 node ids).  The tables
-// are sized above the number of distinct keys a workgroup can insert, except
-// where a caller falls back to a global atomic when a table is full.
-__device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key) {
-    const u32 size = 1u << bits;
-    u32 h = (key * 0x9E3779B1u) >> (32u - bits);
-    for (u32 p = 0; p < size; ++p) {
-        const u32 k = atomicCAS(&keys[h], kNone, key);
-        if (k == kNone || k == key) return h;
-        h = (h + 1u) & (size - 1u);
-    }
-    return kNone;
-}
-
 constexpr u32 kClaimBuf = 2048;  // claims staged per workgroup before one flush
 constexpr u32 kSlotBits = 9;     // > 256 distinct leaves per tile
 constexpr u32 kNodeBits = 8;     // inner nodes with new voxels per workgroup
+
+// One level of voxel sampling for a wave: every lane whose node at depth d is
+// inner tests its cell's bit (word = the grid word holding it, loaded by the
+// caller); a clear bit makes the cell a candidate.  Consecutive lanes on the
+// same cell with increasing keys claim once; claims go to the claim table,
+// freshly created entries are staged in LDS, and new-voxel counts per node
+// are summed in LDS.  Must be reached by the whole wave.
+__device__ __forceinline__ void level_claims(const DevTree& t, bool inner, u32 node, u32 d, u32 word,
+                                             u32 qx, u32 qy, u32 qz, u32 key, u32 rgba, u32 lane,
+                                             u32 stripe, u32* s_claims, u32* s_nclaims,
+                                             u32* s_vkey, u32* s_vcnt) {
+    u64 tag = kEmptyTag;
+    if (inner) {
+        const u32 lin = cell_lin(qx, qy, qz, t.Dmax - d, t.r, t.R - 1u);
+        if (!((word >> (lin & 31u)) & 1u)) tag = ((u64)node << 24) | lin;
+    }
+    if (__ballot(tag != kEmptyTag) == 0ull) return;  // no candidate in the wave
+    const u64 ptag = __shfl_up(tag, 1);
+    const u32 pkey = __shfl_up(key, 1);
+    const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
+    bool fresh = false;
+    u32 hslot = 0u;
+    if (cand) fresh = claim_cell(t, tag, ((u64)key << 32) | (u64)rgba, hslot);
+    const u64 fm = __ballot(fresh);
+    if (fm == 0ull) return;
+    const int leader = __ffsll((long long)fm) - 1;
+    u32 off = 0u;
+    if ((int)lane == leader) off = atomicAdd(s_nclaims, (u32)__popcll(fm));
+    off = __shfl(off, leader) + (u32)__popcll(fm & lanes_below(lane));
+    if (fresh) {
+        if (off < kClaimBuf) {
+            s_claims[off] = hslot;
+        } else {  // staging full: append straight to the stripe
+            const u32 pos = atomicAdd(&t.ctr->claim_count[stripe], 1u);
+            if (pos < t.claim_cap)
+                t.claims[(u64)stripe * t.claim_cap + pos] = hslot;
+            else
+                set_status(t, SIMLOD_OVF_BACKLOG);
+        }
+    }
+    const Run vr = lane_runs(fresh ? node : kNone);
+    if (fresh && vr.rank == 0u) {
+        const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
+        if (e != kNone) {
+            atomicAdd(&s_vcnt[e], vr.len);
+        } else if (atomicAdd(&t.newv[node], vr.len) == 0u) {
+            const u32 p = atomicAdd(&t.ctr->vtouched_count, 1u);
+            if (p < t.max_nodes)
+                t.vtouched[p] = node;
+            else
+                set_status(t, SIMLOD_OVF_WORK);
+        }
+    }
+}
 
 // Walks each point of W once more from the root.  At every inner node it
 // projects the point into the node's R^3 grid (cell = (q >> (Dmax - d)) &
@@ -414,7 +745,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
     __shared__ u32 s_nclaims, s_flush;
     Counters* ctr = t.ctr;
-    if (wg_skip(ctr, 1u)) return;
+    if (wg_skip(ctr, nullptr)) return;
     const u32 tid = threadIdx.x;
     for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
         s_lkey[i] = kNone;
@@ -442,73 +773,64 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             fetch_work(t, batch, S, base_key, j, rec, key);
             quantize3(t, rec, qx, qy, qz);
         }
-        u32 node = 0u;
+        // Path through the node directory: all entries, then all grid blocks,
+        // then all grid words are loaded as independent batches.
+        const u32 D = t.dir_depth;
+        const u32 m = dir_index(t.K, D, qx, qy, qz);
+        u32 e[kDirMaxDepth + 1], w[kDirMaxDepth + 1];
+#pragma unroll
+        for (u32 d = 0; d <= kDirMaxDepth; ++d)
+            e[d] = (valid && d <= D) ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
+#pragma unroll
+        for (u32 d = 0; d <= kDirMaxDepth; ++d)
+            w[d] = (e[d] != kNone && (e[d] & kDirInner)) ? t.grid[e[d] & ~kDirInner] : kNone;
+#pragma unroll
+        for (u32 d = 0; d <= kDirMaxDepth; ++d) {
+            const u32 lin = d <= t.Dmax ? cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) : 0u;
+            w[d] = w[d] != kNone ? reinterpret_cast<const u32*>(block_ptr(t, w[d]))[lin >> 5] : ~0u;
+        }
+        u32 leaf = kNone;
         bool desc = valid;
-        for (u32 d = 0; d <= t.Dmax; ++d) {  // inner nodes exist only above Dmax
+#pragma unroll
+        for (u32 d = 0; d <= kDirMaxDepth; ++d) {
+            if (d <= D) {  // uniform
+                const bool inner = desc && e[d] != kNone && (e[d] & kDirInner);
+                if (desc && !inner) {
+                    if (e[d] == kNone) set_status(t, SIMLOD_OVF_INTERNAL);
+                    leaf = e[d] == kNone ? 0u : e[d];
+                    desc = false;
+                }
+                level_claims(t, inner, e[d] & ~kDirInner, d, w[d], qx, qy, qz, key, rec.w, lane,
+                             stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
+            }
+        }
+        // Below the directory: dependent walk through child[].
+        u32 node = 0u;
+        if (desc) node = t.child[e[D] & ~kDirInner] + octant_of(qx, qy, qz, t.K - 1u - D);
+        for (u32 d = D + 1u; d <= t.Dmax; ++d) {
             const u32 c = desc && d < t.Dmax ? t.child[node] : 0u;
             const bool inner = desc && c != 0u;
-            if (__ballot(inner) == 0ull) break;
-            u64 tag = kEmptyTag;
-            if (inner) {
-                const u32 shift = t.Dmax - d;
-                const u32 lin = ((qx >> shift) & rmask) | (((qy >> shift) & rmask) << t.r) |
-                                (((qz >> shift) & rmask) << (2u * t.r));
-                const u32 word = grid_of(t, node)[lin >> 5];
-                if (!((word >> (lin & 31u)) & 1u)) tag = ((u64)node << 24) | lin;
-            }
-            const u64 ptag = __shfl_up(tag, 1);
-            const u32 pkey = __shfl_up(key, 1);
-            const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
-            bool fresh = false;
-            u32 hslot = 0u;
-            if (cand) fresh = claim_cell(t, tag, ((u64)key << 32) | (u64)rec.w, hslot);
-            // stage the claim in LDS (one LDS atomic per wave)
-            const u64 fm = __ballot(fresh);
-            if (fm) {
-                const int leader = __ffsll((long long)fm) - 1;
-                u32 off = 0u;
-                if ((int)lane == leader) off = atomicAdd(&s_nclaims, (u32)__popcll(fm));
-                off = __shfl(off, leader) + (u32)__popcll(fm & lanes_below(lane));
-                if (fresh) {
-                    if (off < kClaimBuf) {
-                        s_claims[off] = hslot;
-                    } else {  // staging full: append straight to the stripe
-                        const u32 pos = atomicAdd(&ctr->claim_count[stripe], 1u);
-                        if (pos < t.claim_cap)
-                            t.claims[(u64)stripe * t.claim_cap + pos] = hslot;
-                        else
-                            set_status(t, SIMLOD_OVF_BACKLOG);
-                    }
-                }
-            }
-            // count new voxels per node in LDS
-            const Run vr = lane_runs(fresh ? node : kNone);
-            if (fresh && vr.rank == 0u) {
-                const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
-                if (e != kNone) {
-                    atomicAdd(&s_vcnt[e], vr.len);
-                } else if (atomicAdd(&t.newv[node], vr.len) == 0u) {
-                    const u32 p = atomicAdd(&ctr->vtouched_count, 1u);
-                    if (p < t.max_nodes)
-                        t.vtouched[p] = node;
-                    else
-                        set_status(t, SIMLOD_OVF_WORK);
-                }
-            }
-            if (inner)
-                node = c + octant_of(qx, qy, qz, t.K - 1u - d);
-            else
+            if (desc && !inner) {
+                leaf = node;
                 desc = false;
+            }
+            if (__ballot(inner) == 0ull) break;
+            u32 word = ~0u;
+            if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
+            level_claims(t, inner, node, d, word, qx, qy, qz, key, rec.w, lane, stripe, s_claims,
+                         &s_nclaims, s_vkey, s_vcnt);
+            if (inner) node = c + octant_of(qx, qy, qz, t.K - 1u - d);
         }
+        if (desc) leaf = node;
         // leaf slots: LDS histogram of the tile, one global atomic per leaf
-        const u32 leaf = valid ? node : kNone;
+        if (!valid) leaf = kNone;
         const Run r = lane_runs(leaf);
-        u32 e = kNone, r0 = 0u;
+        u32 le = kNone, r0 = 0u;
         if (leaf != kNone && r.rank == 0u) {
-            e = lds_find_or_insert(s_lkey, kSlotBits, leaf);  // never full: <= 256 keys
-            r0 = atomicAdd(&s_lcnt[e], r.len);
+            le = lds_find_or_insert(s_lkey, kSlotBits, leaf);  // never full: <= 256 keys
+            r0 = atomicAdd(&s_lcnt[le], r.len);
         }
-        e = __shfl(e, r.head);
+        le = __shfl(le, r.head);
         r0 = __shfl(r0, r.head) + r.rank;
         __syncthreads();
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
@@ -517,7 +839,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         }
         __syncthreads();
         if (valid) {
-            const u32 slot = s_lbase[e] + r0;
+            const u32 slot = s_lbase[le] + r0;
             const u32 ci = slot / t.C;
             if (ci < t.nchunks[leaf]) {
                 const u32 cb = table_of(t, leaf)[ci];
@@ -623,11 +945,9 @@ __global__ void k_finish(DevTree t) {
     Counters* c = t.ctr;
     if (c->status) return;
     if (c->pool_top < 0) c->pool_top = 0;
-    u32 rounds = 1u;
-    for (u32 k = 1; k <= (u32)kMaxRounds; ++k)
-        if (c->split_any[k]) rounds = k + 1u;
     u32 claims = 0u;
     for (u32 k = 0; k < kStripes; ++k) claims += min(c->claim_count[k], t.claim_cap);
+    const u32 rounds = 1u + c->build_rounds;
     c->last_rounds = rounds;
     c->last_spilled = c->spill_count;
     c->last_new_voxels = claims;
@@ -640,13 +960,21 @@ __global__ void k_finish(DevTree t) {
     c->spill_count = 0u;
     c->final_count = 0u;
     c->vtouched_count = 0u;
+    c->touched_count = 0u;
     for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
-    c->touched_count[0] = c->touched_count[1] = 0u;
-    for (u32 k = 0; k < (u32)kMaxRounds + 2u; ++k) c->split_any[k] = 0u;
+    c->pending_count[0] = c->pending_count[1] = 0u;
+    c->hist_top = 0u;
+    c->zero_count = 0u;
+    c->build_rounds = 0u;
 }
 
 // ------------------------------------------------------- reset / export
 __global__ void k_fill_u64(u64* p, u64 n, u64 v) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(u32* p, u64 n, u32 v) {
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
         p[i] = v;
 }
@@ -660,13 +988,14 @@ __global__ void k_reset(DevTree t) {
     t.child[0] = 0u;
     t.count[0] = 0u;
     t.cnt[0] = 0u;
-    t.birth[0] = 0u;
+    t.hslot[0] = kNone;
     t.geo[0] = make_uint4(0u, 0u, 0u, 0u);
     t.grid[0] = kNone;
     t.tab[0] = kNone;
     t.tabcap[0] = 0u;
     t.nchunks[0] = 0u;
     t.newv[0] = 0u;
+    t.dir[0] = 0u;  // the root, a leaf
 }
 
 // Copies the records and keys of the listed nodes to out[first[i] ...].
@@ -696,20 +1025,28 @@ static inline u32 grid_for(u64 items, u32 lo, u32 hi) {
     return (u32)((g + 7u) & ~7ull);
 }
 
-hipError_t launch_count(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
-                        u32 epoch, hipStream_t s) {
-    u32 g = round == 1u ? grid_for(n, 8, 4096) : (round == 2u ? grid_for(n, 64, 2048)
-                                                            : grid_for(n / 4u, 32, 512));
-    hipLaunchKernelGGL(k_count, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key, round, epoch);
+u32 expansion_rounds(u32 max_depth) { return 1u + (max_depth + kHistLevels - 1u) / kHistLevels; }
+
+hipError_t launch_count_leaves(const DevTree& t, const uint4* batch, u32 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_leaves, dim3(grid_for(n, 8, 4096)), dim3(kWG), 0, s, t, batch, n);
     return hipGetLastError();
 }
-hipError_t launch_split(const DevTree& t, u32 round, u32 epoch, u32 n, hipStream_t s) {
-    u32 g = round == 1u ? grid_for((u64)n / 64u, 64, 1024) : 256u;
-    hipLaunchKernelGGL(k_split, dim3(g), dim3(kWG), 0, s, t, round, epoch);
+hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s) {
+    hipLaunchKernelGGL(k_split_leaves, dim3(grid_for((u64)n / 64u, 64, 1024)), dim3(kWG), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_count_hist(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
+                             hipStream_t s) {
+    const u32 g = round == 2u ? grid_for((u64)n + 65536u, 64, 4096) : grid_for((u64)n / 4u, 32, 1024);
+    hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key, round);
+    return hipGetLastError();
+}
+hipError_t launch_build(const DevTree& t, u32 round, hipStream_t s) {
+    hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, t, round);
     return hipGetLastError();
 }
 hipError_t launch_alloc(const DevTree& t, u32 voxels, hipStream_t s) {
-    hipLaunchKernelGGL(k_alloc, dim3(256), dim3(kWG), 0, s, t, voxels);
+    hipLaunchKernelGGL(k_alloc, dim3(voxels ? 256 : 1024), dim3(kWG), 0, s, t, voxels);
     return hipGetLastError();
 }
 hipError_t launch_sample_store(const DevTree& t, const uint4* batch, u32 n, u32 base_key,
@@ -731,6 +1068,9 @@ hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {
     u32 g = (u32)std::min<u64>((hash_entries + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kWG), 0, s, t.htag, hash_entries, kEmptyTag);
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kWG), 0, s, t.hval, hash_entries, ~0ull);
+    const u64 dir_entries = dir_offset(t.dir_depth + 1u);
+    const u32 gd = (u32)std::min<u64>((dir_entries + kWG - 1) / kWG, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gd), dim3(kWG), 0, s, t.dir, dir_entries, kNone);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, t);
     return hipGetLastError();
 }

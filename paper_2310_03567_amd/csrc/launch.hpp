@@ -9,9 +9,12 @@
 
 namespace simlod {
 
-hipError_t launch_count(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
-                        u32 epoch, hipStream_t s);
-hipError_t launch_split(const DevTree& t, u32 round, u32 epoch, u32 n, hipStream_t s);
+u32 expansion_rounds(u32 max_depth);
+hipError_t launch_count_leaves(const DevTree& t, const uint4* batch, u32 n, hipStream_t s);
+hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s);
+hipError_t launch_count_hist(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
+                             hipStream_t s);
+hipError_t launch_build(const DevTree& t, u32 round, hipStream_t s);
 hipError_t launch_alloc(const DevTree& t, u32 voxels, hipStream_t s);
 hipError_t launch_sample_store(const DevTree& t, const uint4* batch, u32 n, u32 base_key,
                                hipStream_t s);

@@ -9,9 +9,9 @@
 //   count[n]    points of a leaf / voxels of an inner node; during the store
 //               passes it is also the slot counter (section "Storing Points
 //               and Voxels": numPoints / numVoxels)
-//   cnt[n]      expansion counter of the current round (section "Expanding
-//               the Octree": point counter), zero outside a round
-//   birth[n]    epoch of the round whose split created the node
+//   cnt[n]      first-round counter (section "Expanding the Octree": point
+//               counter), zero outside a pass
+//   hslot[n]    histogram slot while the leaf is a pending root, else kNone
 //   geo[n]      {origin x, origin y, origin z, depth}, origin in integer
 //               coordinates (units of 2^-K of the root size)
 //   grid[n]     arena block of the R^3 occupancy bitmap (inner nodes)
@@ -20,6 +20,13 @@
 //               the ids of its chunks in list order, so chunk slot/C is one
 //               load away (the chunks are also linked, see below)
 //   newv[n]     voxels claimed for the node in the current pass
+//
+// Node directory: for each depth d <= dir_depth (at most kDirMaxDepth) a
+// dense table of 8^d entries indexed by the Morton code of the node's d-bit
+// integer position; entry = node id, with kDirInner set once the node has
+// children, or kNone where no node exists at that depth.  A point's path down
+// to dir_depth is then dir_depth + 1 independent loads instead of a chain of
+// dependent child-pointer loads; below dir_depth the walk follows child[].
 //
 // Persistent buffer ("arena", section "Persistent Buffer"): one allocation
 // carved into 256-byte blocks by an atomic bump counter; chunks, occupancy
@@ -44,6 +51,17 @@ constexpr u64 kEmptyTag = ~0ull;
 constexpr u32 kBlockBytes = 256;
 constexpr int kMaxRounds = 24;  // >= max_depth + 1
 constexpr u32 kStripes = 8;     // claim-list stripes (one per XCD)
+constexpr u32 kDirMaxDepth = 7;         // deepest level of the node directory
+constexpr u32 kDirInner = 0x80000000u;  // directory entry flag: the node is inner
+
+// Histogram of a pending root: counts of its virtual descendants at
+// kHistLevels levels below it, 8^j counters at level j (j = 1..kHistLevels),
+// indexed by the Morton code of the relative path.
+constexpr u32 kHistLevels = 4;
+constexpr u32 kHistEntries = 8u + 64u + 512u + 4096u;
+__host__ __device__ __forceinline__ u32 hist_level_offset(u32 j) {  // (8^j - 8) / 7
+    return ((1u << (3u * j)) - 8u) / 7u;
+}
 
 // Device-resident counters of one octree.
 struct Counters {
@@ -54,12 +72,15 @@ struct Counters {
     u32 spill_count;     // points moved to the spill buffer this pass
     u32 final_count;     // leaves finalized this pass
     u32 vtouched_count;  // inner nodes that claimed voxels this pass
+    u32 touched_count;   // leaves counted in the first round
     u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
-    u32 touched_count[2];
-    u32 split_any[kMaxRounds + 2];
-    // statistics of the last pass and high-water marks
+    u32 pending_count[2];       // pending roots listed by round k in [k & 1]
+    u32 hist_top;        // histogram slots handed out this pass
+    u32 zero_count;      // occupancy grids to clear before sampling
+    u32 build_rounds;    // histogram rounds that built something this pass
     u32 last_rounds, last_spilled, last_new_voxels;
     u32 max_rounds, max_spilled, max_new_voxels;
+    u32 pad;
     u64 sum_spilled, sum_new_voxels, sum_rounds;
 };
 
@@ -68,7 +89,7 @@ struct DevTree {
     u32* child;
     u32* count;
     u32* cnt;
-    u32* birth;
+    u32* hslot;          // histogram slot of a pending root, kNone otherwise
     uint4* geo;
     u32* grid;
     u32* tab;
@@ -76,6 +97,8 @@ struct DevTree {
     u32* nchunks;
     u32* newv;
     u32 max_nodes;
+    u32* dir;
+    u32 dir_depth;
     Counters* ctr;
     // persistent buffer and chunk pool
     uint8_t* arena;
@@ -86,9 +109,13 @@ struct DevTree {
     uint4* spill_rec;
     u32* spill_key;
     u32 spill_cap;
-    u32* touched[2];
+    u32* touched;        // leaves counted in the first round
     uint2* final_list;   // {leaf, points added}
     u32* vtouched;       // inner nodes with new voxels
+    u32* pending[2];     // pending roots (leaves that must split)
+    u32* zero_list;      // grid blocks of this pass's new inner nodes
+    u32* hist;           // hist_cap slots of kHistEntries counters
+    u32 hist_cap;
     uint8_t* amask[2];   // per work item: counted in the previous round
     u32 active_cap;
     u64* htag;           // voxel claim table: (node << 24 | cell) or empty
@@ -141,6 +168,35 @@ __device__ __forceinline__ u32 quantize(float v, float mn, float scale, u32 K) {
 __device__ __forceinline__ float cell_centre(u32 g, float mn, float size, u32 r, u32 d) {
     float h = ldexpf(size, -(int)(r + d));
     return __fadd_rn(mn, __fmul_rn(__fadd_rn((float)g, 0.5f), h));
+}
+
+// Gathers every third bit (bit 3i -> bit i), the inverse of spread3.
+__host__ __device__ __forceinline__ u32 compact3(u32 x) {
+    x &= 0x09249249u;
+    x = (x ^ (x >> 2)) & 0x030C30C3u;
+    x = (x ^ (x >> 4)) & 0x0300F00Fu;
+    x = (x ^ (x >> 8)) & 0x030000FFu;
+    x = (x ^ (x >> 16)) & 0x000003FFu;
+    return x;
+}
+
+// Interleaves the low 10 bits of x into every third bit (bit i -> bit 3i).
+__host__ __device__ __forceinline__ u32 spread3(u32 x) {
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__host__ __device__ __forceinline__ u32 dir_offset(u32 d) { return ((1u << (3u * d)) - 1u) / 7u; }
+
+// Morton index, at depth d, of the cell holding integer position (x, y, z):
+// bit 3i = x, 3i+1 = y, 3i+2 = z, so index(d + 1) = index(d) * 8 + octant.
+__device__ __forceinline__ u32 dir_index(u32 K, u32 d, u32 qx, u32 qy, u32 qz) {
+    const u32 s = K - d;
+    return d ? (spread3(qx >> s) | (spread3(qy >> s) << 1) | (spread3(qz >> s) << 2)) : 0u;
 }
 
 __device__ __forceinline__ u32 octant_of(u32 qx, u32 qy, u32 qz, u32 bit) {

@@ -26,6 +26,7 @@ ERR_POISONED = -5
 ERR_KEY_SPACE = -6
 
 OVF_NODES, OVF_ARENA, OVF_SPILL, OVF_BACKLOG, OVF_WORK, OVF_HASH = 1, 2, 4, 8, 16, 32
+OVF_INTERNAL, OVF_HIST = 64, 128
 
 KERNEL_NAMES = ("count", "split", "alloc_points", "sample_store", "alloc_voxels",
                 "store_voxels", "finish")
@@ -46,7 +47,7 @@ class Config(ctypes.Structure):
         ("max_depth", ctypes.c_uint32),
         ("chunk_capacity", ctypes.c_uint32),
         ("max_nodes", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("hist_capacity", ctypes.c_uint32),
         ("arena_bytes", ctypes.c_uint64),
         ("max_batch", ctypes.c_uint64),
         ("spill_capacity", ctypes.c_uint64),
@@ -137,7 +138,8 @@ def default_config() -> Config:
 
 def make_config(root_min=(0.0, 0.0, 0.0), root_size=1.0, leaf_capacity=50_000, grid_bits=7,
                 max_depth=16, chunk_capacity=1000, max_nodes=None, arena_bytes=None,
-                max_batch=None, spill_capacity=None, backlog_capacity=None, device=0) -> Config:
+                max_batch=None, spill_capacity=None, backlog_capacity=None, hist_capacity=None,
+                device=0) -> Config:
     cfg = default_config()
     cfg.root_min[:] = [float(v) for v in root_min]
     cfg.root_size = float(root_size)
@@ -148,7 +150,7 @@ def make_config(root_min=(0.0, 0.0, 0.0), root_size=1.0, leaf_capacity=50_000, g
     cfg.device = int(device)
     for name, v in (("max_nodes", max_nodes), ("arena_bytes", arena_bytes),
                     ("max_batch", max_batch), ("spill_capacity", spill_capacity),
-                    ("backlog_capacity", backlog_capacity)):
+                    ("backlog_capacity", backlog_capacity), ("hist_capacity", hist_capacity)):
         if v is not None:
             setattr(cfg, name, int(v))
     return cfg

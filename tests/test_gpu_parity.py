@@ -154,7 +154,7 @@ def test_identical_points_reach_max_depth_on_gpu():
         st = tree.stats()
     assert_trees_equal(got, O1.build(p, cfg))
     assert len(got.nodes) == 1 + 8 * 16 and got.num_voxels == 16
-    assert st["max_rounds"] == 17
+    assert st["max_rounds"] == 1 + 16 // 4  # one flat round, then 4 levels per round
 
 
 def test_empty_and_single_point_batches():
