@@ -670,16 +670,63 @@ constexpr u32 kClaimBuf = 2048;  // claims staged per workgroup before one flush
 constexpr u32 kSlotBits = 9;     // > 256 distinct leaves per tile
 constexpr u32 kNodeBits = 8;     // inner nodes with new voxels per workgroup
 
+constexpr u32 kCandBits = 10;  // claim candidates per tile, deduplicated in LDS
+constexpr u32 kCands = 1u << kCandBits;
+
+// Stages a claim the calling lane created: the claim-table slot goes to the
+// workgroup's LDS buffer (straight to the stripe when that is full) and the
+// node's new-voxel count is summed in LDS.
+__device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 node, u32 stripe,
+                                            u32* s_claims, u32* s_nclaims, u32* s_vkey,
+                                            u32* s_vcnt) {
+    const u32 off = atomicAdd(s_nclaims, 1u);
+    if (off < kClaimBuf) {
+        s_claims[off] = hslot;
+    } else {
+        const u32 pos = atomicAdd(&t.ctr->claim_count[stripe], 1u);
+        if (pos < t.claim_cap)
+            t.claims[(u64)stripe * t.claim_cap + pos] = hslot;
+        else
+            set_status(t, SIMLOD_OVF_BACKLOG);
+    }
+    const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
+    if (e != kNone) {
+        atomicAdd(&s_vcnt[e], 1u);
+    } else if (atomicAdd(&t.newv[node], 1u) == 0u) {
+        const u32 p = atomicAdd(&t.ctr->vtouched_count, 1u);
+        if (p < t.max_nodes)
+            t.vtouched[p] = node;
+        else
+            set_status(t, SIMLOD_OVF_WORK);
+    }
+}
+
+// Candidate table of one tile: (node << 24 | cell) -> min (key << 32 | rgba).
+__device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 val) {
+    u32 h = (u32)(mix64(tag) >> (64u - kCandBits));
+    for (u32 p = 0; p < 64u; ++p) {
+        const u64 cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)kEmptyTag,
+                                  (unsigned long long)tag);
+        if (cur == kEmptyTag || cur == tag) {
+            atomicMin((unsigned long long*)&cval[h], (unsigned long long)val);
+            return true;
+        }
+        h = (h + 1u) & (kCands - 1u);
+    }
+    return false;
+}
+
 // One level of voxel sampling for a wave: every lane whose node at depth d is
 // inner tests its cell's bit (word = the grid word holding it, loaded by the
 // caller); a clear bit makes the cell a candidate.  Consecutive lanes on the
-// same cell with increasing keys claim once; claims go to the claim table,
-// freshly created entries are staged in LDS, and new-voxel counts per node
-// are summed in LDS.  Must be reached by the whole wave.
-__device__ __forceinline__ void level_claims(const DevTree& t, bool inner, u32 node, u32 d, u32 word,
-                                             u32 qx, u32 qy, u32 qz, u32 key, u32 rgba, u32 lane,
-                                             u32 stripe, u32* s_claims, u32* s_nclaims,
-                                             u32* s_vkey, u32* s_vcnt) {
+// same cell with increasing keys add it once; candidates are merged in the
+// tile's LDS table (smallest key per cell) and claimed globally, all at once,
+// after the traversal.  Must be reached by the whole wave.
+__device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
+                                                 u32 word, u32 qx, u32 qy, u32 qz, u32 key,
+                                                 u32 rgba, u32 lane, u64* ctag, u64* cval,
+                                                 u32 stripe, u32* s_claims, u32* s_nclaims,
+                                                 u32* s_vkey, u32* s_vcnt) {
     u64 tag = kEmptyTag;
     if (inner) {
         const u32 lin = cell_lin(qx, qy, qz, t.Dmax - d, t.r, t.R - 1u);
@@ -689,38 +736,51 @@ __device__ __forceinline__ void level_claims(const DevTree& t, bool inner, u32 n
     const u64 ptag = __shfl_up(tag, 1);
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
-    bool fresh = false;
-    u32 hslot = 0u;
-    if (cand) fresh = claim_cell(t, tag, ((u64)key << 32) | (u64)rgba, hslot);
-    const u64 fm = __ballot(fresh);
-    if (fm == 0ull) return;
-    const int leader = __ffsll((long long)fm) - 1;
-    u32 off = 0u;
-    if ((int)lane == leader) off = atomicAdd(s_nclaims, (u32)__popcll(fm));
-    off = __shfl(off, leader) + (u32)__popcll(fm & lanes_below(lane));
-    if (fresh) {
-        if (off < kClaimBuf) {
-            s_claims[off] = hslot;
-        } else {  // staging full: append straight to the stripe
-            const u32 pos = atomicAdd(&t.ctr->claim_count[stripe], 1u);
-            if (pos < t.claim_cap)
-                t.claims[(u64)stripe * t.claim_cap + pos] = hslot;
-            else
-                set_status(t, SIMLOD_OVF_BACKLOG);
-        }
+    const u64 val = ((u64)key << 32) | (u64)rgba;
+    if (cand && !cand_insert(ctag, cval, tag, val)) {  // table full: claim right away
+        u32 hslot;
+        if (claim_cell(t, tag, val, hslot))
+            stage_claim(t, hslot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt);
     }
-    const Run vr = lane_runs(fresh ? node : kNone);
-    if (fresh && vr.rank == 0u) {
-        const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
-        if (e != kNone) {
-            atomicAdd(&s_vcnt[e], vr.len);
-        } else if (atomicAdd(&t.newv[node], vr.len) == 0u) {
-            const u32 p = atomicAdd(&t.ctr->vtouched_count, 1u);
-            if (p < t.max_nodes)
-                t.vtouched[p] = node;
-            else
-                set_status(t, SIMLOD_OVF_WORK);
+}
+
+// Claims every candidate of the tile in the global claim table; the lookups
+// of all a thread's entries are issued together.  Clears the LDS table.
+__device__ __forceinline__ void claim_candidates(const DevTree& t, u64* ctag, u64* cval,
+                                                 u32 stripe, u32* s_claims, u32* s_nclaims,
+                                                 u32* s_vkey, u32* s_vcnt) {
+    constexpr u32 kPer = kCands / 256u;
+    u64 tg[kPer], vl[kPer], cur[kPer];
+    u32 hh[kPer];
+#pragma unroll
+    for (u32 k = 0; k < kPer; ++k) {
+        const u32 i = threadIdx.x + k * 256u;
+        tg[k] = ctag[i];
+        vl[k] = cval[i];
+        ctag[i] = kEmptyTag;
+        cval[i] = ~0ull;
+        hh[k] = (u32)mix64(tg[k]) & t.hmask;
+    }
+#pragma unroll
+    for (u32 k = 0; k < kPer; ++k) cur[k] = tg[k] != kEmptyTag ? t.htag[hh[k]] : 0ull;
+#pragma unroll
+    for (u32 k = 0; k < kPer; ++k)
+        if (tg[k] != kEmptyTag && cur[k] == kEmptyTag)
+            cur[k] = atomicCAS((unsigned long long*)&t.htag[hh[k]], (unsigned long long)kEmptyTag,
+                               (unsigned long long)tg[k]);
+#pragma unroll
+    for (u32 k = 0; k < kPer; ++k) {
+        if (tg[k] == kEmptyTag) continue;
+        bool fresh;
+        u32 hslot = hh[k];
+        if (cur[k] == kEmptyTag || cur[k] == tg[k]) {
+            atomicMin((unsigned long long*)&t.hval[hh[k]], (unsigned long long)vl[k]);
+            fresh = cur[k] == kEmptyTag;
+        } else {
+            fresh = claim_cell(t, tg[k], vl[k], hslot);  // collision: probe onwards
         }
+        if (fresh)
+            stage_claim(t, hslot, (u32)(tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey, s_vcnt);
     }
 }
 
@@ -743,10 +803,15 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
     __shared__ u32 s_claims[kClaimBuf];
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
+    __shared__ u64 s_ctag[kCands], s_cval[kCands];
     __shared__ u32 s_nclaims, s_flush;
     Counters* ctr = t.ctr;
     if (wg_skip(ctr, nullptr)) return;
     const u32 tid = threadIdx.x;
+    for (u32 i = tid; i < kCands; i += kWG) {
+        s_ctag[i] = kEmptyTag;
+        s_cval[i] = ~0ull;
+    }
     for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
         s_lkey[i] = kNone;
         s_lcnt[i] = 0u;
@@ -791,18 +856,21 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         }
         u32 leaf = kNone;
         bool desc = valid;
+        for (u32 d = 0; d <= D; ++d) {  // rolled: d is uniform, entries picked by select
+            u32 ed = e[0], wd = w[0];
 #pragma unroll
-        for (u32 d = 0; d <= kDirMaxDepth; ++d) {
-            if (d <= D) {  // uniform
-                const bool inner = desc && e[d] != kNone && (e[d] & kDirInner);
-                if (desc && !inner) {
-                    if (e[d] == kNone) set_status(t, SIMLOD_OVF_INTERNAL);
-                    leaf = e[d] == kNone ? 0u : e[d];
-                    desc = false;
-                }
-                level_claims(t, inner, e[d] & ~kDirInner, d, w[d], qx, qy, qz, key, rec.w, lane,
-                             stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
+            for (u32 k = 1; k <= kDirMaxDepth; ++k) {
+                ed = d == k ? e[k] : ed;
+                wd = d == k ? w[k] : wd;
             }
+            const bool inner = desc && ed != kNone && (ed & kDirInner);
+            if (desc && !inner) {
+                if (ed == kNone) set_status(t, SIMLOD_OVF_INTERNAL);
+                leaf = ed == kNone ? 0u : ed;
+                desc = false;
+            }
+            level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w, lane,
+                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
@@ -817,11 +885,14 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             if (__ballot(inner) == 0ull) break;
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
-            level_claims(t, inner, node, d, word, qx, qy, qz, key, rec.w, lane, stripe, s_claims,
-                         &s_nclaims, s_vkey, s_vcnt);
+            level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, lane, s_ctag,
+                             s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
             if (inner) node = c + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
+        // the tile's candidates, claimed together
+        __syncthreads();
+        claim_candidates(t, s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
         // leaf slots: LDS histogram of the tile, one global atomic per leaf
         if (!valid) leaf = kNone;
         const Run r = lane_runs(leaf);
@@ -882,12 +953,29 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
 }
 
 // ------------------------------------------------------- voxel stores
+constexpr u32 kWordBits = 9;  // grid words touched per tile, merged in LDS
+
 // One thread per claimed cell: the voxel (cell centre, colour of the
 // smallest-key point) goes to the node's next voxel slot, the cell's bit is
-// set, and the claim-table entry is cleared for the next pass.
+// set, and the claim-table entry is cleared for the next pass.  Slots are
+// reserved per (workgroup, node) after an LDS histogram of the tile, and the
+// tile's bits are OR-ed per grid word in LDS before one atomic per word.
 __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
+    __shared__ u32 s_nkey[1u << kSlotBits], s_ncnt[1u << kSlotBits], s_nbase[1u << kSlotBits];
+    __shared__ u64 s_wkey[1u << kWordBits];
+    __shared__ u32 s_wbits[1u << kWordBits];
     Counters* ctr = t.ctr;
-    if (__builtin_amdgcn_readfirstlane(ctr->status)) return;  // wave-uniform
+    if (wg_skip(ctr, nullptr)) return;
+    const u32 tid = threadIdx.x;
+    for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
+        s_nkey[i] = kNone;
+        s_ncnt[i] = 0u;
+    }
+    for (u32 i = tid; i < (1u << kWordBits); i += kWG) {
+        s_wkey[i] = kEmptyTag;
+        s_wbits[i] = 0u;
+    }
+    __syncthreads();
     u32 pre[kStripes + 1];
     pre[0] = 0u;
     for (u32 s = 0; s < kStripes; ++s) pre[s + 1] = pre[s] + min(ctr->claim_count[s], t.claim_cap);
@@ -895,7 +983,7 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
     const u32 rmask = t.R - 1u;
     const u32 step = gridDim.x * kWG;
     for (u32 base = blockIdx.x * kWG; base < n; base += step) {
-        const u32 i = base + threadIdx.x;
+        const u32 i = base + tid;
         const bool valid = i < n;
         u32 h = 0u, node = kNone, lin = 0u;
         u64 val = 0ull;
@@ -908,12 +996,48 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
             node = (u32)(tag >> 24);
             lin = (u32)tag & 0xFFFFFFu;
         }
+        // slot reservation: LDS histogram per node, one global atomic per node
         const Run r = lane_runs(node);
-        u32 sb = 0u;
-        if (valid && r.rank == 0u) sb = atomicAdd(&t.count[node], r.len);
-        sb = __shfl(sb, r.head);
+        u32 ne = kNone, r0 = 0u;
+        if (node != kNone && r.rank == 0u) {
+            ne = lds_find_or_insert(s_nkey, kSlotBits, node);  // never full: <= 256 keys
+            r0 = atomicAdd(&s_ncnt[ne], r.len);
+        }
+        ne = __shfl(ne, r.head);
+        r0 = __shfl(r0, r.head) + r.rank;
+        // grid bits: OR per word in LDS
         if (valid) {
-            const u32 slot = sb + r.rank;
+            const u64 wkey = ((u64)node << 32) | (lin >> 5);
+            u32 we = (u32)(mix64(wkey) >> (64u - kWordBits));
+            bool done = false;
+            for (u32 p = 0; p < (1u << kWordBits) && !done; ++p) {
+                const u64 cur = atomicCAS((unsigned long long*)&s_wkey[we],
+                                          (unsigned long long)kEmptyTag, (unsigned long long)wkey);
+                if (cur == kEmptyTag || cur == wkey) {
+                    atomicOr(&s_wbits[we], 1u << (lin & 31u));
+                    done = true;
+                } else {
+                    we = (we + 1u) & ((1u << kWordBits) - 1u);
+                }
+            }
+            if (!done) atomicOr(&grid_of(t, node)[lin >> 5], 1u << (lin & 31u));
+        }
+        __syncthreads();
+        for (u32 e = tid; e < (1u << kSlotBits); e += kWG) {
+            const u32 k = s_nkey[e];
+            if (k != kNone) s_nbase[e] = atomicAdd(&t.count[k], s_ncnt[e]);
+        }
+        for (u32 e = tid; e < (1u << kWordBits); e += kWG) {
+            const u64 wk = s_wkey[e];
+            if (wk != kEmptyTag) {
+                atomicOr(&grid_of(t, (u32)(wk >> 32))[(u32)wk], s_wbits[e]);
+                s_wkey[e] = kEmptyTag;
+                s_wbits[e] = 0u;
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            const u32 slot = s_nbase[ne] + r0;
             const uint4 g = t.geo[node];
             const u32 d = g.w;
             const u32 shift = t.Dmax - d;
@@ -932,10 +1056,15 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
             } else {
                 set_status(t, SIMLOD_OVF_ARENA);
             }
-            atomicOr(&grid_of(t, node)[lin >> 5], 1u << (lin & 31u));
             t.htag[h] = kEmptyTag;
             t.hval[h] = ~0ull;
         }
+        __syncthreads();
+        for (u32 e = tid; e < (1u << kSlotBits); e += kWG) {
+            s_nkey[e] = kNone;
+            s_ncnt[e] = 0u;
+        }
+        __syncthreads();
     }
 }
 
@@ -1028,7 +1157,7 @@ static inline u32 grid_for(u64 items, u32 lo, u32 hi) {
 u32 expansion_rounds(u32 max_depth) { return 1u + (max_depth + kHistLevels - 1u) / kHistLevels; }
 
 hipError_t launch_count_leaves(const DevTree& t, const uint4* batch, u32 n, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_leaves, dim3(grid_for(n, 8, 4096)), dim3(kWG), 0, s, t, batch, n);
+    hipLaunchKernelGGL(k_count_leaves, dim3(grid_for(n, 8, 1024)), dim3(kWG), 0, s, t, batch, n);
     return hipGetLastError();
 }
 hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s) {
@@ -1037,7 +1166,7 @@ hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s) {
 }
 hipError_t launch_count_hist(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
                              hipStream_t s) {
-    const u32 g = round == 2u ? grid_for((u64)n + 65536u, 64, 4096) : grid_for((u64)n / 4u, 32, 1024);
+    const u32 g = round == 2u ? grid_for((u64)n + 65536u, 64, 1024) : grid_for((u64)n / 4u, 32, 512);
     hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key, round);
     return hipGetLastError();
 }
@@ -1051,12 +1180,12 @@ hipError_t launch_alloc(const DevTree& t, u32 voxels, hipStream_t s) {
 }
 hipError_t launch_sample_store(const DevTree& t, const uint4* batch, u32 n, u32 base_key,
                                hipStream_t s) {
-    u32 g = grid_for((u64)n + 4096u, 64, 4096);
+    u32 g = grid_for((u64)n + 4096u, 64, 1024);
     hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key);
     return hipGetLastError();
 }
 hipError_t launch_store_voxels(const DevTree& t, u32 n, hipStream_t s) {
-    u32 g = grid_for(n, 64, 2048);
+    u32 g = grid_for(n, 64, 1024);
     hipLaunchKernelGGL(k_store_voxels, dim3(g), dim3(kWG), 0, s, t);
     return hipGetLastError();
 }

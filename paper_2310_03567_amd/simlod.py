@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsimlod.so")
+# SIMLOD_LIBRARY selects another build of the same library (same ABI).
+LIB_PATH = os.environ.get("SIMLOD_LIBRARY") or os.path.join(_HERE, "libsimlod.so")
 
 OK = 0
 ERR_INVALID_ARGUMENT = -1
