@@ -46,8 +46,32 @@ SAMPLE_STORE_BYTES_PER_ITEM = 36
 SAMPLE_STORE_BYTES_PER_SPILLED = 4
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_store_aerial_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03567_amd", "csrc", "kernels.hip")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per k_sample_store launch from the committed rocprofv3 summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the summary
+    was taken on a different kernel source."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith(" "))
+    want = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernels_sha256", "").strip() != want:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def generate(name, n):
@@ -86,6 +110,9 @@ def main():
     ap.add_argument("--workload", default="aerial", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (an HBM "
+                         "counter reference for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -107,6 +134,12 @@ def main():
 
     dev = torch.from_numpy(pts.view(np.uint8).reshape(-1)).to("cuda:0")
     torch.cuda.synchronize()
+    if args.copy_calibration_mb:
+        a = torch.empty(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     stream = torch.cuda.current_stream()
     cfg = simlod.make_config(root_min=w["root_min"], root_size=w["root_size"],
                              max_nodes=1 << 20, arena_bytes=24 << 30, max_batch=B,
@@ -160,9 +193,11 @@ def main():
                      + SAMPLE_STORE_BYTES_PER_SPILLED * st["sum_spilled"])
         avg_s = kt[1] / 1e3 / kt[0]
         achieved = alg_bytes / kt[0] / avg_s / 1e9
+        traffic = measured_traffic()
         roofline = {"kernel": "k_sample_store", "bound": "hbm", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "launches": kt[0], "avg_launch_us": round(avg_s * 1e6, 2),
+                    "traffic": None if traffic is None else int(traffic),
+                    "launches": kt[0], "avg_launch_us": round(avg_s * 1e6, 2),
                     "bytes_per_launch": int(alg_bytes / kt[0])}
     else:
         roofline = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,

@@ -201,10 +201,10 @@ hipError_t enqueue_pass(simlod_octree* h, const uint4* batch, u32 n, u32 base_ke
     if (e == hipSuccess)
         e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(t, n, s); });
     for (u32 k = 2; k <= rounds && e == hipSuccess; ++k) {
-        e = timed(h, SIMLOD_KERNEL_COUNT, s,
+        e = timed(h, SIMLOD_KERNEL_COUNT_HIST, s,
                   [&] { return launch_count_hist(t, batch, n, base_key, k, s); });
         if (e == hipSuccess)
-            e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_build(t, k, s); });
+            e = timed(h, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(t, k, s); });
     }
     if (e == hipSuccess)
         e = timed(h, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(t, 0u, s); });

@@ -744,43 +744,51 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     }
 }
 
-// Claims every candidate of the tile in the global claim table; the lookups
-// of all a thread's entries are issued together.  Clears the LDS table.
-__device__ __forceinline__ void claim_candidates(const DevTree& t, u64* ctag, u64* cval,
-                                                 u32 stripe, u32* s_claims, u32* s_nclaims,
-                                                 u32* s_vkey, u32* s_vcnt) {
-    constexpr u32 kPer = kCands / 256u;
-    u64 tg[kPer], vl[kPer], cur[kPer];
-    u32 hh[kPer];
+// Claims of one tile, in two halves so that other global atomics can share
+// the round trip: claim_issue takes a thread's entries of the LDS candidate
+// table (clearing them) and issues their claim-table CASes; claim_resolve
+// min-reduces the values and stages the claims this workgroup created.
+constexpr u32 kCandPer = kCands / 256u;
+struct ClaimBatch {
+    u64 tg[kCandPer], vl[kCandPer], cur[kCandPer];
+    u32 hh[kCandPer];
+};
+
+__device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval, ClaimBatch& b) {
 #pragma unroll
-    for (u32 k = 0; k < kPer; ++k) {
+    for (u32 k = 0; k < kCandPer; ++k) {
         const u32 i = threadIdx.x + k * 256u;
-        tg[k] = ctag[i];
-        vl[k] = cval[i];
+        b.tg[k] = ctag[i];
+        b.vl[k] = cval[i];
         ctag[i] = kEmptyTag;
         cval[i] = ~0ull;
-        hh[k] = (u32)mix64(tg[k]) & t.hmask;
+        b.hh[k] = (u32)mix64(b.tg[k]) & t.hmask;
     }
 #pragma unroll
-    for (u32 k = 0; k < kPer; ++k) cur[k] = tg[k] != kEmptyTag ? t.htag[hh[k]] : 0ull;
+    for (u32 k = 0; k < kCandPer; ++k)
+        b.cur[k] = b.tg[k] != kEmptyTag
+                       ? atomicCAS((unsigned long long*)&t.htag[b.hh[k]],
+                                   (unsigned long long)kEmptyTag, (unsigned long long)b.tg[k])
+                       : 0ull;
+}
+
+__device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch& b, u32 stripe,
+                                              u32* s_claims, u32* s_nclaims, u32* s_vkey,
+                                              u32* s_vcnt) {
 #pragma unroll
-    for (u32 k = 0; k < kPer; ++k)
-        if (tg[k] != kEmptyTag && cur[k] == kEmptyTag)
-            cur[k] = atomicCAS((unsigned long long*)&t.htag[hh[k]], (unsigned long long)kEmptyTag,
-                               (unsigned long long)tg[k]);
-#pragma unroll
-    for (u32 k = 0; k < kPer; ++k) {
-        if (tg[k] == kEmptyTag) continue;
+    for (u32 k = 0; k < kCandPer; ++k) {
+        if (b.tg[k] == kEmptyTag) continue;
         bool fresh;
-        u32 hslot = hh[k];
-        if (cur[k] == kEmptyTag || cur[k] == tg[k]) {
-            atomicMin((unsigned long long*)&t.hval[hh[k]], (unsigned long long)vl[k]);
-            fresh = cur[k] == kEmptyTag;
+        u32 hslot = b.hh[k];
+        if (b.cur[k] == kEmptyTag || b.cur[k] == b.tg[k]) {
+            atomicMin((unsigned long long*)&t.hval[hslot], (unsigned long long)b.vl[k]);
+            fresh = b.cur[k] == kEmptyTag;
         } else {
-            fresh = claim_cell(t, tg[k], vl[k], hslot);  // collision: probe onwards
+            fresh = claim_cell(t, b.tg[k], b.vl[k], hslot);  // collision: probe onwards
         }
         if (fresh)
-            stage_claim(t, hslot, (u32)(tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey, s_vcnt);
+            stage_claim(t, hslot, (u32)(b.tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey,
+                        s_vcnt);
     }
 }
 
@@ -829,15 +837,16 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
     const u32 rmask = t.R - 1u;
     const u32 stripe = blockIdx.x % kStripes;
     const u32 step = gridDim.x * kWG;
-    for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
-        const u32 j = base + tid;
-        const bool valid = j < nwork;
-        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
-        u32 key = 0u, qx = 0u, qy = 0u, qz = 0u;
-        if (valid) {
-            fetch_work(t, batch, S, base_key, j, rec, key);
-            quantize3(t, rec, qx, qy, qz);
-        }
+    u32 base = xcd_block() * kWG;
+    uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
+    u32 key_n = 0u;
+    if (base + tid < nwork) fetch_work(t, batch, S, base_key, base + tid, rec_n, key_n);
+    for (; base < nwork; base += step) {
+        const bool valid = base + tid < nwork;
+        const uint4 rec = rec_n;
+        const u32 key = key_n;
+        u32 qx = 0u, qy = 0u, qz = 0u;
+        if (valid) quantize3(t, rec, qx, qy, qz);
         // Path through the node directory: all entries, then all grid blocks,
         // then all grid words are loaded as independent batches.
         const u32 D = t.dir_depth;
@@ -890,10 +899,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             if (inner) node = c + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
-        // the tile's candidates, claimed together
-        __syncthreads();
-        claim_candidates(t, s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
-        // leaf slots: LDS histogram of the tile, one global atomic per leaf
+        // leaf slots: LDS histogram of the tile
         if (!valid) leaf = kNone;
         const Run r = lane_runs(leaf);
         u32 le = kNone, r0 = 0u;
@@ -904,30 +910,34 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         le = __shfl(le, r.head);
         r0 = __shfl(r0, r.head) + r.rank;
         __syncthreads();
+        // one round trip for the tile: claim CASes, one slot reservation per
+        // leaf, and the next tile's records
+        ClaimBatch cb;
+        claim_issue(t, s_ctag, s_cval, cb);
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
+            s_lkey[i] = kNone;
+            s_lcnt[i] = 0u;
         }
+        if (base + step + tid < nwork)
+            fetch_work(t, batch, S, base_key, base + step + tid, rec_n, key_n);
+        claim_resolve(t, cb, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
         __syncthreads();
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
             const u32 ci = slot / t.C;
             if (ci < t.nchunks[leaf]) {
-                const u32 cb = table_of(t, leaf)[ci];
+                const u32 cbk = table_of(t, leaf)[ci];
                 const u32 o = slot - ci * t.C;
-                chunk_recs(t, cb)[o] = rec;
-                chunk_keys(t, cb)[o] = key;
+                chunk_recs(t, cbk)[o] = rec;
+                chunk_keys(t, cbk)[o] = key;
             } else {
                 set_status(t, SIMLOD_OVF_ARENA);
             }
         }
-        __syncthreads();
-        for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
-            s_lkey[i] = kNone;
-            s_lcnt[i] = 0u;
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // flush staged claims (one atomic per workgroup) and per-node counts
     const u32 nc = min(s_nclaims, kClaimBuf);
     if (tid == 0) s_flush = nc ? atomicAdd(&ctr->claim_count[stripe], nc) : 0u;
