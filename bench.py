@@ -30,14 +30,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Every workload uses the paper's octree parameters (T = 50,000, 128^3 grids,
+# chunks of 1,000) and Dmax = 16; the capacities are the launch configuration
+# the benchmark (and the full-size parity tests) run.
 WORKLOADS = {
     "aerial": dict(
         desc="aerial-LiDAR-shaped heightfield, 100M points, 1M-point batches, Morton-shuffled",
-        points=100_000_000, batch=1_000_000, root_min=(0.0, 0.0, 0.0), root_size=1024.0),
+        points=100_000_000, batch=1_000_000, root_min=(0.0, 0.0, 0.0), root_size=1024.0,
+        caps=dict(max_nodes=1 << 20, arena_bytes=24 << 30, spill_capacity=16 << 20,
+                  backlog_capacity=10_000_000)),
+    "dense": dict(
+        desc="dense-scan-shaped building, 1B points on 2,000 primitives with Gaussian "
+             "hotspots, 10M-point batches in scan order",
+        points=1_000_000_000, batch=10_000_000, root_min=(0.0, 0.0, 0.0), root_size=64.0,
+        caps=dict(max_nodes=1 << 21, arena_bytes=96 << 30, spill_capacity=64 << 20,
+                  backlog_capacity=40_000_000, hist_capacity=1 << 15)),
     "planes": dict(
         desc="3 planes + 5% noise in the unit cube, 1M points, 100k-point batches",
-        points=1_000_000, batch=100_000, root_min=(0.0, 0.0, 0.0), root_size=1.0),
+        points=1_000_000, batch=100_000, root_min=(0.0, 0.0, 0.0), root_size=1.0,
+        caps=dict(max_nodes=1 << 16, arena_bytes=2 << 30, spill_capacity=1 << 20,
+                  backlog_capacity=1 << 20)),
 }
+
+
+def octree_config(name):
+    """simlod config of a workload's launch configuration."""
+    from paper_2310_03567_amd import simlod
+
+    w = WORKLOADS[name]
+    return simlod.make_config(root_min=w["root_min"], root_size=w["root_size"],
+                              max_batch=w["batch"], **w["caps"])
 
 # Algorithmic bytes of k_sample_store per work item: read the 16-byte record,
 # write the 16-byte record and its 4-byte key into the leaf chunk; a spilled
@@ -74,12 +96,15 @@ def measured_traffic():
         return None
 
 
-def generate(name, n):
+def generate(name, n=None):
     import pointgen
 
     w = WORKLOADS[name]
+    n = w["points"] if n is None else n
     if name == "aerial":
         return pointgen.aerial(n, seed=1, order="morton_shuffled", batch=w["batch"])
+    if name == "dense":
+        return pointgen.dense_scan(n, seed=2)
     return pointgen.tiny_planes(n, seed=0)
 
 
@@ -129,7 +154,7 @@ def main():
     steps = min(args.steps, nb_total)
     warm = min(args.warmup, nb_total)
     t0 = time.perf_counter()
-    pts = generate(args.workload, w["points"])
+    pts = generate(args.workload)
     log(f"generated {len(pts)} points in {time.perf_counter() - t0:.1f} s")
 
     dev = torch.from_numpy(pts.view(np.uint8).reshape(-1)).to("cuda:0")
@@ -141,10 +166,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     stream = torch.cuda.current_stream()
-    cfg = simlod.make_config(root_min=w["root_min"], root_size=w["root_size"],
-                             max_nodes=1 << 20, arena_bytes=24 << 30, max_batch=B,
-                             spill_capacity=16 << 20, backlog_capacity=10_000_000)
-    tree = simlod.Octree(cfg)
+    tree = simlod.Octree(octree_config(args.workload))
 
     def batch(i):
         return dev[i * B * 16:(i + 1) * B * 16]

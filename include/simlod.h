@@ -62,6 +62,7 @@ extern "C" {
 #define SIMLOD_ERR_CAPACITY (-4)         /* a device-side capacity overflowed    */
 #define SIMLOD_ERR_POISONED (-5)         /* handle unusable after an earlier error */
 #define SIMLOD_ERR_KEY_SPACE (-6)        /* more than 2^32 - 1 points in one octree */
+#define SIMLOD_ERR_NOT_FOUND (-7)        /* simlod_snapshot_subtree: no node with that path */
 
 /* Bits of simlod_stats_data.status_bits (device-side overflow causes). */
 #define SIMLOD_OVF_NODES 0x1u   /* node table (max_nodes) full            */
@@ -229,11 +230,24 @@ int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, v
 
 /* Canonical export.  Synchronizes the handle's last stream.  Call with all
  * three buffer pointers NULL to obtain the sizes, then with host buffers of
- * at least those sizes (the octree must not change in between).  The
- * library allocates temporary device memory here.
- * Errors: INVALID_ARGUMENT (only some buffers NULL), POISONED, CAPACITY,
- * OUT_OF_MEMORY, HIP. */
+ * at least those sizes (the octree must not change in between).  With only
+ * `nodes` set, fills the node records alone (no record copy).  The library
+ * allocates temporary device memory here.
+ * Errors: INVALID_ARGUMENT (records or keys NULL but not both, or set
+ * without nodes), POISONED, CAPACITY, OUT_OF_MEMORY, HIP. */
 int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s);
+
+/* Canonical export of one subtree: the node with `path` (1 = root, then
+ * parent * 8 + octant per level, the same paths the snapshot records carry)
+ * and all its descendants, in the same form and with the same two-call
+ * pattern as simlod_snapshot; paths and depths stay absolute, `first`
+ * counts from the subtree's first record.  Reads part of a large octree
+ * (the intermediate results the paper displays while loading, section
+ * "Introduction") without copying all of it to the host.
+ * Errors: as simlod_snapshot; INVALID_ARGUMENT for a value that is not a
+ * path or is deeper than max_depth; NOT_FOUND when an ancestor of the node
+ * is a leaf (the node does not exist yet). */
+int simlod_snapshot_subtree(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s);
 
 /* Counters; synchronizes the handle's last stream.  Works on a poisoned
  * handle (status_bits tells why). */
@@ -251,7 +265,7 @@ int simlod_destroy(simlod_octree* h);
 
 /* Selects the kernels whose launches later passes bracket with HIP events on
  * the pass's stream: bit k of kernel_mask = SIMLOD_KERNEL_k (0 disables,
- * 0x7F times all).  Clears the accumulated times. */
+ * 0x1FF times all).  Clears the accumulated times. */
 int simlod_set_kernel_timing(simlod_octree* h, uint32_t kernel_mask);
 
 /* Synchronizes and returns the times accumulated since timing was enabled. */
@@ -261,8 +275,9 @@ int simlod_get_kernel_times(simlod_octree* h, simlod_kernel_times* out);
 const char* simlod_status_string(int code);
 
 /* Text naming the HIP call behind the calling thread's most recent
- * SIMLOD_ERR_HIP or SIMLOD_ERR_OUT_OF_MEMORY ("" if none); valid until the
- * thread's next library call. */
+ * SIMLOD_ERR_HIP or SIMLOD_ERR_OUT_OF_MEMORY, or the path behind its most
+ * recent SIMLOD_ERR_NOT_FOUND ("" if none); valid until the thread's next
+ * library call. */
 const char* simlod_last_error(void);
 
 #ifdef __cplusplus

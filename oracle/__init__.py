@@ -34,5 +34,7 @@ from .canonical import (  # noqa: F401
     NODE_DTYPE,
     POINT_DTYPE,
     assert_trees_equal,
+    path_depth,
+    subtree,
     trees_equal,
 )

@@ -120,6 +120,39 @@ class CanonicalTree:
         return {int(p): i for i, p in enumerate(self.nodes["path"])}
 
 
+def path_depth(path: int) -> int:
+    """Depth of the node with ``path`` (1 = root, 3 bits per level below)."""
+    path = int(path)
+    if path < 1 or (path.bit_length() - 1) % 3:
+        raise ValueError(f"not a node path: {path}")
+    return (path.bit_length() - 1) // 3
+
+
+def subtree(tree: CanonicalTree, path: int) -> CanonicalTree | None:
+    """The subtree rooted at the node with ``path``, in canonical form (paths
+    and depths absolute, ``first`` counted from the subtree's first record),
+    or None when the tree has no such node.
+
+    In preorder a subtree is the node followed by every later node whose path
+    extends it, so it is one contiguous run of nodes and of records.
+    """
+    d = path_depth(path)
+    hit = np.nonzero(tree.nodes["path"] == np.uint64(path))[0]
+    if not len(hit):
+        return None
+    i = int(hit[0])
+    depth = tree.nodes["depth"].astype(np.int64)
+    # descendants follow directly and are deeper; the run ends at the first
+    # node at the subtree root's depth or above
+    later = np.nonzero(depth[i + 1:] <= d)[0]
+    j = i + 1 + int(later[0]) if len(later) else len(tree.nodes)
+    nodes = tree.nodes[i:j].copy()
+    a = int(nodes["first"][0])
+    b = int(nodes["first"][-1]) + int(nodes["count"][-1])
+    nodes["first"] -= np.uint64(a)
+    return CanonicalTree(nodes=nodes, records=tree.records[a:b], keys=tree.keys[a:b])
+
+
 def trees_equal(a: CanonicalTree, b: CanonicalTree) -> bool:
     return (
         a.nodes.shape == b.nodes.shape

@@ -227,6 +227,59 @@ int orc_insert(orc_tree* t, const orc_rec* pts, uint64_t n) {
     return 0;
 }
 
+/* Inserts only the points of a batch that fall in the region of the node
+   with `path` (1 = root, parent * 8 + octant below; depth = number of
+   octant digits, at most Dmax), each with the key it has in the whole
+   sequence; keys of the skipped points are consumed all the same.
+
+   By the recursive definition, a node's subtree depends only on the points
+   of its region.  Fed with exactly those points, every ancestor of the node
+   holds all of them, so when they number more than T the ancestors are
+   inner, the node exists, and its subtree is the one the whole sequence
+   gives (provided the node exists there too); with T or fewer the root
+   stays a leaf holding them, which is the node's content in the whole tree
+   when the node is a leaf there.  This lets single subtrees of clouds too
+   large for one oracle run be checked one at a time.
+   Returns 0, -1 on allocation failure / key overflow, -2 on a bad path. */
+int orc_insert_region(orc_tree* t, const orc_rec* pts, uint64_t n, uint64_t path) {
+    if (t->error) return -1;
+    uint32_t d = 0;
+    uint64_t digits[32];
+    for (uint64_t p = path; p > 1; p >>= 3) {
+        if (d >= t->Dmax || d >= 32) return -2;
+        digits[d++] = p & 7u;
+    }
+    if (path < 1) return -2;
+    uint64_t p = path;
+    while (p > 7) p >>= 3;
+    if (p != 1) return -2;
+    if (t->total + n > 0xFFFFFFFFull) {
+        t->error = 1;
+        return -1;
+    }
+    t->voxels_created_last = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const orc_rec* rc = &pts[i];
+        uint32_t q[3];
+        q[0] = orc_quant(rc->x, t->mn[0], t->scale, t->K);
+        q[1] = orc_quant(rc->y, t->mn[1], t->scale, t->K);
+        q[2] = orc_quant(rc->z, t->mn[2], t->scale, t->K);
+        int inside = 1;
+        for (uint32_t j = 0; j < d && inside; ++j) {
+            uint32_t b = t->K - 1u - j;
+            uint32_t oct = ((q[0] >> b) & 1u) | (((q[1] >> b) & 1u) << 1) | (((q[2] >> b) & 1u) << 2);
+            inside = oct == digits[d - 1 - j];
+        }
+        if (!inside) continue;
+        if (orc_insert_from(t, 0, rc, (uint32_t)(t->total + i))) {
+            t->error = 1;
+            return -1;
+        }
+    }
+    t->total += n;
+    return 0;
+}
+
 uint64_t orc_voxels_created_last(const orc_tree* t) { return t->voxels_created_last; }
 
 /* Sizes of the canonical form. */

@@ -14,7 +14,7 @@ import threading
 
 import numpy as np
 
-from .canonical import NODE_DTYPE, POINT_DTYPE, CanonicalTree, LodConfig
+from .canonical import NODE_DTYPE, POINT_DTYPE, CanonicalTree, LodConfig, path_depth, subtree
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "incremental.c")
@@ -47,6 +47,9 @@ def _load():
             lib.orc_destroy.argtypes = [ctypes.c_void_p]
             lib.orc_insert.restype = ctypes.c_int
             lib.orc_insert.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
+            lib.orc_insert_region.restype = ctypes.c_int
+            lib.orc_insert_region.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.c_uint64]
             lib.orc_voxels_created_last.restype = ctypes.c_uint64
             lib.orc_voxels_created_last.argtypes = [ctypes.c_void_p]
             lib.orc_sizes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
@@ -90,6 +93,34 @@ class IncrementalOracle:
             raise RuntimeError("oracle insert failed (allocation or key overflow)")
         self.total += len(pts)
         self.voxels_created_last = int(self._lib.orc_voxels_created_last(self._h))
+
+    def insert_region(self, points: np.ndarray, path: int) -> None:
+        """Inserts only the points in the region of node ``path``, keeping
+        their keys in the whole sequence (see ``orc_insert_region``)."""
+        pts = np.ascontiguousarray(points, dtype=POINT_DTYPE)
+        rc = self._lib.orc_insert_region(self._h, pts.ctypes.data, len(pts), int(path))
+        if rc == -2:
+            raise ValueError(f"bad node path {path}")
+        if rc != 0:
+            raise RuntimeError("oracle insert failed (allocation or key overflow)")
+        self.total += len(pts)
+        self.voxels_created_last = int(self._lib.orc_voxels_created_last(self._h))
+
+    def region_subtree(self, path: int) -> CanonicalTree:
+        """After ``insert_region(.., path)`` calls only: the subtree of node
+        ``path`` in canonical form (absolute paths and depths).  If the
+        region's points were too few to split the root, that is one leaf
+        holding them."""
+        t = self.canonical()
+        s = subtree(t, path)
+        if s is not None:
+            return s
+        if len(t.nodes) != 1 or not t.nodes["is_leaf"][0]:
+            raise RuntimeError("region tree lacks the node although its root split")
+        nodes = t.nodes.copy()
+        nodes["path"] = path
+        nodes["depth"] = path_depth(path)
+        return CanonicalTree(nodes=nodes, records=t.records, keys=t.keys)
 
     def canonical(self) -> CanonicalTree:
         nn = ctypes.c_uint64()

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "launch.hpp"
@@ -447,57 +448,98 @@ int simlod_sync(simlod_octree* h) {
     return sync_handle(h);
 }
 
-int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
+namespace {
+
+// Canonical export of the subtree rooted at the node with `root_path`.
+int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s) {
     if (!h || !s) return SIMLOD_ERR_INVALID_ARGUMENT;
     const int nulls = (s->nodes == nullptr) + (s->records == nullptr) + (s->keys == nullptr);
-    if (nulls != 0 && nulls != 3) return SIMLOD_ERR_INVALID_ARGUMENT;
+    const bool nodes_only = nulls == 2 && s->nodes != nullptr;
+    if (nulls != 0 && nulls != 3 && !nodes_only) return SIMLOD_ERR_INVALID_ARGUMENT;
+    // path: a leading 1, then one octant digit per level below the root
+    u32 depth = 0;
+    u32 digits[32];
+    for (u64 p = root_path; p > 1; p >>= 3) {
+        if (depth >= h->cfg.max_depth) {
+            std::snprintf(g_last_error, sizeof(g_last_error), "path %llu is deeper than max_depth",
+                          (unsigned long long)root_path);
+            return SIMLOD_ERR_INVALID_ARGUMENT;
+        }
+        digits[depth++] = (u32)(p & 7u);
+    }
+    if (root_path == 0 || (root_path >> (3 * depth)) != 1) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%llu is not a node path",
+                      (unsigned long long)root_path);
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
     DeviceGuard guard(h->device);
     if (h->poisoned) return SIMLOD_ERR_POISONED;
     int rc = sync_handle(h);
     if (rc) return rc;
     clear_stale_error();
     HostNodes hn;
-    rc = read_nodes(h, hn, nulls == 0);
+    rc = read_nodes(h, hn, true);
     if (rc) return rc;
     const u32 nn = (u32)hn.child.size();
-    u64 npts = 0, nvox = 0;
-    for (u32 i = 0; i < nn; ++i) (hn.child[i] ? nvox : npts) += hn.count[i];
-    if (nulls == 3) {
-        s->num_nodes = nn;
-        s->num_points = npts;
-        s->num_voxels = nvox;
-        s->num_records = npts + nvox;
-        return SIMLOD_OK;
+    u32 root = 0;
+    for (u32 j = 0; j < depth; ++j) {
+        if (root >= nn) return SIMLOD_ERR_HIP;
+        if (!hn.child[root]) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "no node with path %llu (a leaf at depth %u)",
+                          (unsigned long long)root_path, j);
+            return SIMLOD_ERR_NOT_FOUND;
+        }
+        root = hn.child[root] + digits[depth - 1 - j];
     }
     // Preorder, children in octant order.
     std::vector<u32> order;
     std::vector<u64> first;
     std::vector<u64> path;
-    order.reserve(nn);
-    first.reserve(nn);
-    path.reserve(nn);
     std::vector<std::pair<u32, u64>> stack;
-    stack.push_back({0u, 1ull});
-    u64 written = 0;
+    stack.push_back({root, root_path});
+    u64 written = 0, npts = 0, nvox = 0;
     while (!stack.empty()) {
         auto [node, p] = stack.back();
         stack.pop_back();
-        if (node >= nn) return SIMLOD_ERR_HIP;
+        if (node >= nn || order.size() >= nn) return SIMLOD_ERR_HIP;
         order.push_back(node);
         first.push_back(written);
         path.push_back(p);
         written += hn.count[node];
+        (hn.child[node] ? nvox : npts) += hn.count[node];
         if (hn.child[node])
             for (int o = 7; o >= 0; --o) stack.push_back({hn.child[node] + (u32)o, p * 8 + (u64)o});
     }
-    if (order.size() != nn || written != npts + nvox) return SIMLOD_ERR_HIP;
+    const u32 ns = (u32)order.size();
+    s->num_nodes = ns;
+    s->num_points = npts;
+    s->num_voxels = nvox;
+    s->num_records = written;
+    auto fill_nodes = [&]() {
+        for (u32 i = 0; i < ns; ++i) {
+            const u32 node = order[i];
+            simlod_node_record& r = s->nodes[i];
+            r.path = path[i];
+            r.first = first[i];
+            r.count = hn.count[node];
+            r.depth = (uint8_t)hn.geo[node].w;
+            r.is_leaf = hn.child[node] ? 0 : 1;
+            r.reserved = 0;
+        }
+    };
+    if (nulls == 3) return SIMLOD_OK;
+    if (nodes_only) {
+        fill_nodes();
+        return SIMLOD_OK;
+    }
     u32* d_nodes = nullptr;
     u64* d_first = nullptr;
     uint4* d_rec = nullptr;
     u32* d_key = nullptr;
     const u64 nrec = std::max<u64>(written, 1);
-    bool ok = hipMalloc((void**)&d_nodes, nn * 4ull) == hipSuccess &&
-              hipMalloc((void**)&d_first, nn * 8ull) == hipSuccess &&
+    bool ok = hipMalloc((void**)&d_nodes, ns * 4ull) == hipSuccess &&
+              hipMalloc((void**)&d_first, ns * 8ull) == hipSuccess &&
               hipMalloc((void**)&d_rec, nrec * 16ull) == hipSuccess &&
               hipMalloc((void**)&d_key, nrec * 4ull) == hipSuccess;
     std::vector<uint4> rec;
@@ -505,9 +547,9 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
     if (ok) {
         rec.resize(written);
         key.resize(written);
-        ok = hipMemcpy(d_nodes, order.data(), nn * 4ull, hipMemcpyHostToDevice) == hipSuccess &&
-             hipMemcpy(d_first, first.data(), nn * 8ull, hipMemcpyHostToDevice) == hipSuccess &&
-             launch_gather(h->t, d_nodes, d_first, nn, d_rec, d_key, nullptr) == hipSuccess &&
+        ok = hipMemcpy(d_nodes, order.data(), ns * 4ull, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(d_first, first.data(), ns * 8ull, hipMemcpyHostToDevice) == hipSuccess &&
+             launch_gather(h->t, d_nodes, d_first, ns, d_rec, d_key, nullptr) == hipSuccess &&
              hipMemcpy(rec.data(), d_rec, written * 16ull, hipMemcpyDeviceToHost) == hipSuccess &&
              hipMemcpy(key.data(), d_key, written * 4ull, hipMemcpyDeviceToHost) == hipSuccess;
     }
@@ -519,25 +561,21 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
     (void)hipFree(d_rec);
     (void)hipFree(d_key);
     if (!ok) return oom ? SIMLOD_ERR_OUT_OF_MEMORY : SIMLOD_ERR_HIP;
-    // Canonical order inside a node: by key.
-    std::vector<u32> perm;
-    for (u32 i = 0; i < nn; ++i) {
-        const u32 node = order[i];
-        const u64 f = first[i];
-        const u32 c = hn.count[node];
-        simlod_node_record& r = s->nodes[i];
-        r.path = path[i];
-        r.first = f;
-        r.count = c;
-        r.depth = (uint8_t)hn.geo[node].w;
-        r.is_leaf = hn.child[node] ? 0 : 1;
-        r.reserved = 0;
-        bool sorted = true;
-        for (u32 j = 1; j < c && sorted; ++j) sorted = key[f + j - 1] < key[f + j];
-        if (sorted) {
-            std::memcpy(s->records + f, rec.data() + f, c * 16ull);
-            std::memcpy(s->keys + f, key.data() + f, c * 4ull);
-        } else {
+    fill_nodes();
+    // Canonical order inside a node: by key.  Nodes are independent; large
+    // exports sort them on several host threads.
+    auto sort_nodes = [&](u32 lo, u32 hi) {
+        std::vector<u32> perm;
+        for (u32 i = lo; i < hi; ++i) {
+            const u64 f = first[i];
+            const u32 c = hn.count[order[i]];
+            bool sorted = true;
+            for (u32 j = 1; j < c && sorted; ++j) sorted = key[f + j - 1] < key[f + j];
+            if (sorted) {
+                std::memcpy(s->records + f, rec.data() + f, c * 16ull);
+                std::memcpy(s->keys + f, key.data() + f, c * 4ull);
+                continue;
+            }
             perm.resize(c);
             std::iota(perm.begin(), perm.end(), 0u);
             std::sort(perm.begin(), perm.end(),
@@ -547,12 +585,37 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
                 s->keys[f + j] = key[f + perm[j]];
             }
         }
+    };
+    const u32 hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const u32 nthreads = written >= (1u << 22) ? std::min<u32>(hw, ns) : 1u;
+    if (nthreads <= 1) {
+        sort_nodes(0, ns);
+    } else {
+        // split the node range into pieces of about equal record counts
+        std::vector<std::thread> pool;
+        u32 lo = 0;
+        for (u32 t = 0; t < nthreads && lo < ns; ++t) {
+            const u64 target = written * (t + 1) / nthreads;
+            u32 hi = lo;
+            while (hi < ns && (t + 1 == nthreads || first[hi] < target)) ++hi;
+            if (hi == lo) hi = lo + 1;
+            pool.emplace_back(sort_nodes, lo, hi);
+            lo = hi;
+        }
+        for (auto& th : pool) th.join();
+        if (lo < ns) sort_nodes(lo, ns);
     }
-    s->num_nodes = nn;
-    s->num_points = npts;
-    s->num_voxels = nvox;
-    s->num_records = written;
     return SIMLOD_OK;
+}
+
+}  // namespace
+
+int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
+    return export_subtree(h, 1, s);
+}
+
+int simlod_snapshot_subtree(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s) {
+    return export_subtree(h, path, s);
 }
 
 int simlod_stats(simlod_octree* h, simlod_stats_data* st) {
@@ -654,6 +717,7 @@ const char* simlod_status_string(int code) {
         case SIMLOD_ERR_CAPACITY: return "device-side capacity exceeded (handle poisoned)";
         case SIMLOD_ERR_POISONED: return "handle poisoned by an earlier error";
         case SIMLOD_ERR_KEY_SPACE: return "more than 2^32-1 points in one octree";
+        case SIMLOD_ERR_NOT_FOUND: return "no node with that path";
         default: return "unknown status";
     }
 }

@@ -25,6 +25,7 @@ ERR_HIP = -3
 ERR_CAPACITY = -4
 ERR_POISONED = -5
 ERR_KEY_SPACE = -6
+ERR_NOT_FOUND = -7
 
 OVF_NODES, OVF_ARENA, OVF_SPILL, OVF_BACKLOG, OVF_WORK, OVF_HASH = 1, 2, 4, 8, 16, 32
 OVF_INTERNAL, OVF_HIST = 64, 128
@@ -88,6 +89,8 @@ EXPORTS = {
     "simlod_insert_batch": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p],
                             ctypes.c_int),
     "simlod_snapshot": ([ctypes.c_void_p, ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
+    "simlod_snapshot_subtree": ([ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_stats": ([ctypes.c_void_p, ctypes.POINTER(StatsData)], ctypes.c_int),
     "simlod_sync": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -127,7 +130,8 @@ def status_string(code: int) -> str:
 
 def _check(code: int, what: str) -> None:
     if code != OK:
-        detail = lib.simlod_last_error().decode() if code in (ERR_HIP, ERR_OUT_OF_MEMORY) else ""
+        detail = (lib.simlod_last_error().decode()
+                  if code in (ERR_HIP, ERR_OUT_OF_MEMORY, ERR_NOT_FOUND) else "")
         raise SimlodError(code, f"{what} [{detail}]" if detail else what)
 
 
@@ -206,18 +210,25 @@ def insert_batch(handle: int, points, stream=None) -> None:
     del keep
 
 
-def snapshot(handle: int):
-    """Canonical export: (nodes NODE_DTYPE, records POINT_DTYPE, keys uint32)."""
+def snapshot(handle: int, path: int | None = None, nodes_only: bool = False):
+    """Canonical export: (nodes NODE_DTYPE, records POINT_DTYPE, keys uint32)
+    of the whole octree, or of the subtree of the node with ``path``; with
+    ``nodes_only`` the records and keys come back empty."""
+    if path is None:
+        call, name = (lambda b: lib.simlod_snapshot(handle, b)), "simlod_snapshot"
+    else:
+        call, name = (lambda b: lib.simlod_snapshot_subtree(handle, path, b)), "simlod_snapshot_subtree"
     s = SnapshotBuffers()
-    _check(lib.simlod_snapshot(handle, ctypes.byref(s)), "simlod_snapshot (sizes)")
-    nodes = np.zeros(s.num_nodes, dtype=NODE_DTYPE)
-    records = np.zeros(s.num_records, dtype=POINT_DTYPE)
-    keys = np.zeros(s.num_records, dtype=np.uint32)
+    _check(call(ctypes.byref(s)), name + " (sizes)")
+    nodes = np.empty(s.num_nodes, dtype=NODE_DTYPE)
+    nrec = 0 if nodes_only else s.num_records
+    records = np.empty(nrec, dtype=POINT_DTYPE)
+    keys = np.empty(nrec, dtype=np.uint32)
     s.nodes = nodes.ctypes.data
-    s.records = records.ctypes.data
-    s.keys = keys.ctypes.data
-    _check(lib.simlod_snapshot(handle, ctypes.byref(s)), "simlod_snapshot")
-    return nodes[: s.num_nodes], records[: s.num_records], keys[: s.num_records]
+    s.records = None if nodes_only else records.ctypes.data
+    s.keys = None if nodes_only else keys.ctypes.data
+    _check(call(ctypes.byref(s)), name)
+    return nodes[: s.num_nodes], records[:nrec], keys[:nrec]
 
 
 def stats(handle: int) -> dict:
@@ -271,8 +282,8 @@ class Octree:
     def insert(self, points, stream=None) -> None:
         insert_batch(self.handle, points, stream)
 
-    def snapshot(self) -> Snapshot:
-        return Snapshot(*snapshot(self.handle))
+    def snapshot(self, path: int | None = None, nodes_only: bool = False) -> Snapshot:
+        return Snapshot(*snapshot(self.handle, path, nodes_only))
 
     def stats(self) -> dict:
         return stats(self.handle)

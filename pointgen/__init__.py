@@ -16,6 +16,12 @@ shapes, matching sizes in order of magnitude only):
   colour from height; batches of 1M cut from Morton order and shuffled
   (seed 1).  Stands in for aerial LiDAR (the paper's Morro Bay and the
   outskirts of Retz).
+* ``dense_scan`` -- 1B points on the 2,000 primitives (slabs, walls, furniture
+  boxes) of a synthetic 60 x 60 x 15 m building in a 64 m cube, with 200
+  Gaussian hotspots (sigma 0.5 m, 20x peak density), colour per primitive
+  plus jitter, in scan-like primitive-by-primitive order; batches of 10M
+  (seed 2).  Stands in for the terrestrial and photogrammetry scans
+  (Endeavor, Chiller, Meroe, the town centre of Retz).
 """
 
 from __future__ import annotations
@@ -57,6 +63,9 @@ def _load():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_uint64,
                                       ctypes.POINTER(ctypes.c_float), ctypes.c_float, ctypes.c_int]
+            lib.pg_dense_scan.restype = ctypes.c_int
+            lib.pg_dense_scan.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_int]
             _lib = lib
     return _lib
 
@@ -100,6 +109,17 @@ def aerial(n: int = 100_000_000, seed: int = 1, order: str = "morton_shuffled",
                            mn, cube_size, threads or _threads())
     if rc != 0:
         raise RuntimeError(f"pg_aerial failed ({rc})")
+    return out
+
+
+def dense_scan(n: int = 1_000_000_000, seed: int = 2, threads: int | None = None) -> np.ndarray:
+    """Dense-scan-shaped building cloud in scan-like order (see pointgen.c).
+
+    The root cube is [0, 64)^3."""
+    out = np.empty(n, dtype=POINT_DTYPE)
+    rc = _load().pg_dense_scan(out.ctypes.data, n, seed, threads or _threads())
+    if rc != 0:
+        raise RuntimeError(f"pg_dense_scan failed ({rc})")
     return out
 
 

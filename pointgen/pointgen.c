@@ -297,3 +297,263 @@ int pg_aerial(pg_rec* out, uint64_t n, uint64_t seed, double extent, double z0, 
     free(off);
     return reorder(out, n, seed, order, batch, cube_min, cube_size, threads);
 }
+
+/* ------------------------------------------------------------------------
+ * Dense-scan building (the terrestrial-scan-shaped workload).
+ *
+ * A 60 x 60 x 15 m building, footprint [2, 62)^2, floors at z = 2 + 3.75 k,
+ * inside the cube [0, 64)^3, made of 2,000 primitives:
+ *   5 floor / ceiling slabs (60 x 60), 4 outer walls (60 x 15),
+ *   591 interior walls (one storey high, length 1-15 m, normal along x or y),
+ *   1,400 furniture boxes (0.3-2.5 m wide and deep, 0.3-2.2 m high) whose
+ *   4 sides and top are scanned.
+ * Density on every face is a uniform background plus 200 Gaussian hotspots
+ * (sigma 0.5 m, peak 20x the background: mass 19 * 2 pi sigma^2 each), each
+ * centred at an area-uniform position on an area-chosen face and spread in
+ * that face's plane (truncated to the face by rejection).  The n points are
+ * apportioned over faces and hotspots by mass (largest remainder).
+ *
+ * Scan-like order: primitives in a seeded random order; within a primitive
+ * its faces' background points, each face swept in 5 cm strips along its
+ * first axis (random inside a strip), then the bursts of its hotspots.
+ * Colour: a random base colour per primitive plus +-16 jitter per channel,
+ * alpha 255.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    double o[3];     /* corner */
+    int au, av;      /* spanning axes */
+    double lu, lv;   /* extents along au, av */
+    uint32_t prim;
+} pg_face;
+
+typedef struct {
+    uint32_t face;
+    double cu, cv;
+} pg_spot;
+
+#define PG_NPRIM 2000
+#define PG_NSPOT 200
+#define PG_SIGMA 0.5
+#define PG_STRIP 0.05
+
+static pg_face mkface(double x, double y, double z, int au, double lu, int av, double lv,
+                      uint32_t prim) {
+    pg_face f;
+    f.o[0] = x;
+    f.o[1] = y;
+    f.o[2] = z;
+    f.au = au;
+    f.av = av;
+    f.lu = lu;
+    f.lv = lv;
+    f.prim = prim;
+    return f;
+}
+
+/* Faces of the building; returns their number (at most 5 + 4 + 591 + 5 * 1400). */
+static uint32_t building_faces(uint64_t seed, pg_face* F) {
+    uint32_t nf = 0, p = 0;
+    const double lo = 2.0, span = 60.0, storey = 3.75;
+    for (int k = 0; k < 5; ++k, ++p) F[nf++] = mkface(lo, lo, lo + storey * k, 0, span, 1, span, p);
+    F[nf++] = mkface(lo, lo, lo, 1, span, 2, 4 * storey, p++);
+    F[nf++] = mkface(lo + span, lo, lo, 1, span, 2, 4 * storey, p++);
+    F[nf++] = mkface(lo, lo, lo, 0, span, 2, 4 * storey, p++);
+    F[nf++] = mkface(lo, lo + span, lo, 0, span, 2, 4 * storey, p++);
+    for (; p < 600; ++p) {
+        double s = floor(unif(seed, 200, p) * 4.0);
+        int normal_x = unif(seed, 201, p) < 0.5;
+        double len = 1.0 + 14.0 * unif(seed, 202, p);
+        double a = lo + (span - len) * unif(seed, 203, p);
+        double c = lo + 0.1 + (span - 0.2) * unif(seed, 204, p);
+        double z = lo + storey * s;
+        if (normal_x) F[nf++] = mkface(c, a, z, 1, len, 2, storey, p);
+        else F[nf++] = mkface(a, c, z, 0, len, 2, storey, p);
+    }
+    for (; p < PG_NPRIM; ++p) {
+        double s = floor(unif(seed, 210, p) * 4.0);
+        double w = 0.3 + 2.2 * unif(seed, 211, p), d = 0.3 + 2.2 * unif(seed, 212, p);
+        double h = 0.3 + 1.9 * unif(seed, 213, p);
+        double x = lo + (span - w) * unif(seed, 214, p), y = lo + (span - d) * unif(seed, 215, p);
+        double z = lo + storey * s;
+        F[nf++] = mkface(x, y, z, 1, d, 2, h, p);
+        F[nf++] = mkface(x + w, y, z, 1, d, 2, h, p);
+        F[nf++] = mkface(x, y, z, 0, w, 2, h, p);
+        F[nf++] = mkface(x, y + d, z, 0, w, 2, h, p);
+        F[nf++] = mkface(x, y, z + h, 0, w, 1, d, p);
+    }
+    return nf;
+}
+
+typedef struct {
+    double frac;
+    uint32_t idx;
+} pg_rem;
+
+static int rem_cmp(const void* a, const void* b) {
+    const pg_rem* x = (const pg_rem*)a;
+    const pg_rem* y = (const pg_rem*)b;
+    if (x->frac != y->frac) return x->frac > y->frac ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+static uint32_t prim_colour(uint64_t seed, uint32_t prim) {
+    uint64_t h = rnd(seed, 230, prim);
+    return (uint32_t)(h & 0xFFFFFFu);
+}
+
+static pg_rec face_point(const pg_face* f, double u, double v, uint32_t base, uint64_t jit) {
+    double pos[3] = {f->o[0], f->o[1], f->o[2]};
+    pos[f->au] += u;
+    pos[f->av] += v;
+    pg_rec r;
+    r.x = (float)pos[0];
+    r.y = (float)pos[1];
+    r.z = (float)pos[2];
+    double c[3];
+    for (int k = 0; k < 3; ++k)
+        c[k] = (double)((base >> (8 * k)) & 255u) + (double)((jit >> (8 * k)) & 31u) - 16.0;
+    r.rgba = pack_rgba(c[0], c[1], c[2], 255.0);
+    return r;
+}
+
+/* Dense-scan cloud of exactly n points in scan-like order (see above). */
+int pg_dense_scan(pg_rec* out, uint64_t n, uint64_t seed, int threads) {
+    if (threads < 1) threads = 1;
+    const uint32_t max_faces = 5 + 4 + 591 + 5 * 1400;
+    pg_face* F = (pg_face*)malloc(max_faces * sizeof(pg_face));
+    pg_spot* H = (pg_spot*)malloc(PG_NSPOT * sizeof(pg_spot));
+    uint32_t ncomp_max = max_faces + PG_NSPOT;
+    uint64_t* cnt = (uint64_t*)calloc(ncomp_max, 8);
+    uint64_t* off = (uint64_t*)calloc(ncomp_max, 8);
+    pg_rem* rem = (pg_rem*)malloc(ncomp_max * sizeof(pg_rem));
+    uint32_t* perm = (uint32_t*)malloc(PG_NPRIM * 4);
+    uint32_t* first_face = (uint32_t*)malloc((PG_NPRIM + 1) * 4);
+    if (!F || !H || !cnt || !off || !rem || !perm || !first_face) {
+        free(F); free(H); free(cnt); free(off); free(rem); free(perm); free(first_face);
+        return -1;
+    }
+    const uint32_t nf = building_faces(seed, F);
+    const uint32_t nc = nf + PG_NSPOT;
+    double area_sum = 0.0;
+    for (uint32_t i = 0; i < nf; ++i) area_sum += F[i].lu * F[i].lv;
+    /* hotspots: face chosen with probability proportional to area */
+    for (uint32_t k = 0; k < PG_NSPOT; ++k) {
+        double t = unif(seed, 220, k) * area_sum, acc = 0.0;
+        uint32_t f = nf - 1;
+        for (uint32_t i = 0; i < nf; ++i) {
+            acc += F[i].lu * F[i].lv;
+            if (t < acc) {
+                f = i;
+                break;
+            }
+        }
+        H[k].face = f;
+        H[k].cu = unif(seed, 221, k) * F[f].lu;
+        H[k].cv = unif(seed, 222, k) * F[f].lv;
+    }
+    /* apportion n over components by mass, largest remainder */
+    const double spot_mass = 19.0 * 2.0 * 3.14159265358979323846 * PG_SIGMA * PG_SIGMA;
+    const double total = area_sum + spot_mass * PG_NSPOT;
+    uint64_t given = 0;
+    for (uint32_t c = 0; c < nc; ++c) {
+        double m = c < nf ? F[c].lu * F[c].lv : spot_mass;
+        double e = (double)n * m / total;
+        double fl = floor(e);
+        cnt[c] = (uint64_t)fl;
+        given += cnt[c];
+        rem[c].frac = e - fl;
+        rem[c].idx = c;
+    }
+    qsort(rem, nc, sizeof(pg_rem), rem_cmp);
+    for (uint64_t i = 0; given < n; ++i, ++given) cnt[rem[i % nc].idx]++;
+    /* scan order: primitives permuted; faces in order, then hotspot bursts */
+    for (uint32_t p = 0; p < PG_NPRIM; ++p) perm[p] = p;
+    for (uint32_t i = PG_NPRIM; i > 1; --i) {
+        uint32_t j = (uint32_t)(rnd(seed, 223, i) % i);
+        uint32_t t = perm[i - 1];
+        perm[i - 1] = perm[j];
+        perm[j] = t;
+    }
+    for (uint32_t p = 0, i = 0; p <= PG_NPRIM; ++p) {
+        while (i < nf && F[i].prim < p) ++i;
+        first_face[p] = i;
+    }
+    uint64_t w = 0;
+    for (uint32_t pi = 0; pi < PG_NPRIM; ++pi) {
+        uint32_t p = perm[pi];
+        for (uint32_t f = first_face[p]; f < first_face[p + 1]; ++f) {
+            off[f] = w;
+            w += cnt[f];
+        }
+        for (uint32_t k = 0; k < PG_NSPOT; ++k)
+            if (F[H[k].face].prim == p) {
+                off[nf + k] = w;
+                w += cnt[nf + k];
+            }
+    }
+    /* generate: work units of up to 1M points of one component */
+    const uint64_t unit = 1u << 20;
+    uint64_t nunits = 0;
+    for (uint32_t c = 0; c < nc; ++c) nunits += (cnt[c] + unit - 1) / unit;
+    uint64_t* ucomp = (uint64_t*)malloc((nunits + 1) * 16);
+    if (!ucomp || w != n) {
+        free(ucomp); free(F); free(H); free(cnt); free(off); free(rem); free(perm);
+        free(first_face);
+        return -1;
+    }
+    uint64_t u = 0;
+    for (uint32_t c = 0; c < nc; ++c)
+        for (uint64_t j = 0; j < cnt[c]; j += unit) {
+            ucomp[2 * u] = c;
+            ucomp[2 * u + 1] = j;
+            ++u;
+        }
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+    for (int64_t ui = 0; ui < (int64_t)nunits; ++ui) {
+        uint32_t c = (uint32_t)ucomp[2 * ui];
+        uint64_t j0 = ucomp[2 * ui + 1], N = cnt[c];
+        uint64_t j1 = j0 + unit < N ? j0 + unit : N;
+        if (c < nf) {
+            const pg_face* f = &F[c];
+            uint64_t S = (uint64_t)(f->lu / PG_STRIP + 0.5);
+            if (S < 1) S = 1;
+            uint32_t base = prim_colour(seed, f->prim);
+            for (uint64_t j = j0; j < j1; ++j) {
+                uint64_t s = j * S / N;
+                double uu = ((double)s + unif(seed, 1000 + 3 * (uint64_t)c, j)) * (f->lu / (double)S);
+                double vv = unif(seed, 1001 + 3 * (uint64_t)c, j) * f->lv;
+                out[off[c] + j] = face_point(f, uu, vv, base, rnd(seed, 1002 + 3 * (uint64_t)c, j));
+            }
+        } else {
+            const pg_spot* h = &H[c - nf];
+            const pg_face* f = &F[h->face];
+            uint32_t base = prim_colour(seed, f->prim);
+            uint64_t st = 100000 + 4 * (uint64_t)(c - nf);
+            for (uint64_t j = j0; j < j1; ++j) {
+                double uu = h->cu, vv = h->cv;
+                for (uint64_t a = 0; a < 16; ++a) {
+                    double r1 = unif(seed, st, j * 16 + a), r2 = unif(seed, st + 1, j * 16 + a);
+                    double rad = PG_SIGMA * sqrt(-2.0 * log(1.0 - r1));
+                    double gu = h->cu + rad * cos(2.0 * 3.14159265358979323846 * r2);
+                    double gv = h->cv + rad * sin(2.0 * 3.14159265358979323846 * r2);
+                    if (gu >= 0.0 && gu < f->lu && gv >= 0.0 && gv < f->lv) {
+                        uu = gu;
+                        vv = gv;
+                        break;
+                    }
+                }
+                out[off[c] + j] = face_point(f, uu, vv, base, rnd(seed, st + 2, j));
+            }
+        }
+    }
+    free(ucomp);
+    free(F);
+    free(H);
+    free(cnt);
+    free(off);
+    free(rem);
+    free(perm);
+    free(first_face);
+    return 0;
+}

@@ -105,6 +105,7 @@ def test_null_arguments(simlod):
     assert simlod.lib.simlod_create(None, None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_insert_batch(None, None, 0, None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_snapshot(None, None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_snapshot_subtree(None, 1, None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_stats(None, None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_sync(None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_destroy(None) == simlod.OK
@@ -112,7 +113,7 @@ def test_null_arguments(simlod):
 
 
 def test_status_strings(simlod):
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         s = simlod.status_string(code)
         assert s and s != "unknown status"
     assert simlod.status_string(-99) == "unknown status"

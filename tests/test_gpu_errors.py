@@ -101,6 +101,15 @@ def test_snapshot_two_call_contract():
         s = simlod.SnapshotBuffers()
         assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.OK
         assert s.num_records == s.num_points + s.num_voxels and s.num_points == 500
-        buf = np.zeros(1, dtype=simlod.NODE_DTYPE)
-        s.nodes = buf.ctypes.data  # only one of three buffers given
+        nodes = np.zeros(s.num_nodes, dtype=simlod.NODE_DTYPE)
+        recs = np.zeros(s.num_records, dtype=simlod.POINT_DTYPE)
+        # records without keys, or records/keys without nodes: rejected
+        s.nodes, s.records, s.keys = nodes.ctypes.data, recs.ctypes.data, None
         assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.ERR_INVALID_ARGUMENT
+        s.nodes, s.records, s.keys = None, recs.ctypes.data, None
+        assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.ERR_INVALID_ARGUMENT
+        # nodes alone: the node records, nothing else written
+        s.nodes, s.records, s.keys = nodes.ctypes.data, None, None
+        assert simlod.lib.simlod_snapshot(tree.handle, ctypes.byref(s)) == simlod.OK
+        assert s.num_points == 500 and nodes["path"][0] == 1
+        assert int(nodes["count"][nodes["is_leaf"] == 1].sum()) == 500

@@ -196,3 +196,40 @@ def test_reset_restarts_the_sequence():
         tree.insert(to_device(q))
         assert_trees_equal(canonical(tree), O1.build(q, cfg))
         assert tree.stats()["points_inserted"] == 1_500
+
+
+def test_subtree_snapshots_equal_slices_of_the_whole():
+    """simlod_snapshot_subtree returns exactly the whole export's slice for
+    that node (nodes-only mode too); missing and malformed paths fail."""
+    import pointgen
+    from oracle import subtree
+    from paper_2310_03567_amd import simlod
+
+    p = pointgen.tiny_planes(300_000, seed=8)
+    cfg = LodConfig(leaf_capacity=5_000, grid_bits=5, max_depth=9, chunk_capacity=300)
+    log("case: subtree snapshots")
+    with make_octree(cfg, arena_bytes=1 << 30) as tree:
+        insert_batches(tree, to_device(p), [100_000, 200_000])
+        whole = canonical(tree)
+        paths = whole.nodes["path"]
+        rng = np.random.default_rng(9)
+        for path in [1] + rng.choice(paths, 12, replace=False).tolist():
+            s = tree.snapshot(int(path))
+            want = subtree(whole, int(path))
+            assert_trees_equal(canonical_of(s), want, f"path {path}")
+            n = tree.snapshot(int(path), nodes_only=True)
+            assert n.nodes.tobytes() == s.nodes.tobytes() and len(n.records) == 0
+        leaf = int(paths[np.nonzero(whole.nodes["is_leaf"] == 1)[0][0]])
+        with pytest.raises(simlod.SimlodError) as e:
+            tree.snapshot(leaf * 8 + 1)
+        assert e.value.code == simlod.ERR_NOT_FOUND
+        for bad in (0, 2, 5, 8 ** 10):  # not a path, or deeper than max_depth
+            with pytest.raises(simlod.SimlodError) as e:
+                tree.snapshot(bad)
+            assert e.value.code == simlod.ERR_INVALID_ARGUMENT
+
+
+def canonical_of(s):
+    from oracle.canonical import CanonicalTree
+
+    return CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys)

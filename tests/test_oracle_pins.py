@@ -19,7 +19,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import POINT_DTYPE, LodConfig, assert_trees_equal, trees_equal
+from oracle import POINT_DTYPE, LodConfig, assert_trees_equal, subtree, trees_equal
 from oracle import definition as O1
 from oracle.incremental import IncrementalOracle, build_incremental
 from tests.golden_util import check_against_expected, load_fig_update
@@ -255,6 +255,58 @@ def test_partition_invariance():
     ref = O1.build(p, cfg)
     for parts in ([400], [1] * 400, [7, 0, 93, 300], [200, 200], [399, 1]):
         assert_trees_equal(build_incremental(p, cfg, parts), ref, f"parts {parts[:4]}")
+
+
+def test_region_subtrees_equal_subtrees_of_the_definition():
+    """O2 fed only one node's region (keys of the whole sequence kept) gives
+    that node's subtree of O1's whole-sequence octree, for every node: the
+    route by which subtrees of clouds too large for one oracle run are
+    checked."""
+    rng = np.random.default_rng(15)
+    checked = 0
+    for T, r, dmax, n in ((3, 2, 5, 500), (1, 1, 4, 120), (8, 3, 7, 2_000), (5, 0, 3, 300)):
+        cfg = LodConfig(leaf_capacity=T, grid_bits=r, max_depth=dmax, chunk_capacity=3)
+        p = _points(rng.random((n, 3)) ** 3, rng.integers(0, 2**32, n, dtype=np.uint32))
+        full = O1.build(p, cfg)
+        paths = full.nodes["path"]
+        pick = paths if len(paths) <= 40 else rng.choice(paths, 40, replace=False)
+        for path in pick:
+            o = IncrementalOracle(cfg)
+            for part in np.array_split(p, 3):
+                o.insert_region(part, int(path))
+            got = o.region_subtree(int(path))
+            assert o.total == n
+            o.close()
+            want = subtree(full, int(path))
+            assert_trees_equal(got, want, f"T={T} r={r} Dmax={dmax} path={int(path)}")
+            checked += 1
+    assert checked > 60
+    o = IncrementalOracle(LodConfig(max_depth=2))
+    for bad in (0, 2, 7, 8 * 8 * 8 * 8 + 1):  # no leading 1 / too deep
+        with pytest.raises(ValueError):
+            o.insert_region(p[:10], bad)
+    o.close()
+
+
+def test_subtree_slicing_matches_a_fresh_preorder():
+    """``subtree`` of the root is the tree itself; the subtrees of the root's
+    children tile its nodes and records in order."""
+    rng = np.random.default_rng(16)
+    cfg = LodConfig(leaf_capacity=4, grid_bits=2, max_depth=6)
+    p = _points(rng.random((700, 3)) ** 2, rng.integers(0, 2**32, 700, dtype=np.uint32))
+    t = O1.build(p, cfg)
+    assert_trees_equal(subtree(t, 1), t)
+    nodes, recs = 1, int(t.nodes["count"][0])
+    for o in range(8):
+        s = subtree(t, 8 + o)
+        assert s.nodes["path"][0] == 8 + o and s.nodes["first"][0] == 0
+        nodes += len(s.nodes)
+        recs += len(s.records)
+        assert all(int(q) >> (3 * (int(d) - 1)) == 8 + o
+                   for q, d in zip(s.nodes["path"], s.nodes["depth"]))
+    assert nodes == len(t.nodes) and recs == len(t.records)
+    leaf = int(t.nodes["path"][np.nonzero(t.nodes["is_leaf"] == 1)[0][0]])
+    assert subtree(t, leaf * 8 + 3) is None  # below a leaf: no such node
 
 
 def test_permutation_invariance_with_uniform_colour():
