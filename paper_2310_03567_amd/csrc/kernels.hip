@@ -129,17 +129,27 @@ __device__ __forceinline__ bool wg_skip(const Counters* ctr, const u32* skip_if_
 }
 
 // ------------------------------------------------------ LDS aggregation
-// Open-addressing table on u32 keys; returns the entry or kNone when full.
-__device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key) {
+// Open-addressing table on u32 keys; returns the entry, or kNone after
+// max_probe occupied entries (the caller then goes to global memory).  A
+// miss in a nearly full table must stay cheap, so tables that can fill use
+// a short probe limit; `fill` (optional) counts the entries created.
+__device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key,
+                                                  u32 max_probe = 0xFFFFFFFFu,
+                                                  u32* fill = nullptr) {
     const u32 size = 1u << bits;
+    const u32 probes = min(size, max_probe);
     u32 h = (key * 0x9E3779B1u) >> (32u - bits);
-    for (u32 p = 0; p < size; ++p) {
+    for (u32 p = 0; p < probes; ++p) {
         const u32 k = atomicCAS(&keys[h], kNone, key);
+        if (k == kNone && fill) atomicAdd(fill, 1u);
         if (k == kNone || k == key) return h;
         h = (h + 1u) & (size - 1u);
     }
     return kNone;
 }
+
+constexpr u32 kCountProbe = 32;             // probe limit of the counting tables
+constexpr u32 kCountFlushAt = kLds / 2u;    // entries that trigger a flush
 
 // Adds c to a leaf's first-round counter; the first addition lists the leaf.
 __device__ __forceinline__ void count_leaf_global(const DevTree& t, u32 node, u32 c) {
@@ -160,18 +170,41 @@ __device__ __forceinline__ void flush_count(const DevTree& t, u32 key, u32 c) {
         count_leaf_global(t, key, c);
 }
 
+// Called by the whole workgroup after each tile of a counting kernel: once
+// the LDS table holds kCountFlushAt entries, its counts go to global memory
+// and it starts empty, so inserts keep finding free entries within the
+// probe limit however many distinct keys the workgroup meets.
+__device__ __forceinline__ void count_table_tile_end(const DevTree& t, u32* lkey, u32* lval,
+                                                     u32* fill) {
+    __syncthreads();
+    const bool flush = *fill >= kCountFlushAt;
+    __syncthreads();  // every thread has read `fill` before it changes
+    if (!flush) return;
+    for (u32 e = threadIdx.x; e < kLds; e += kWG) {
+        if (lkey[e] != kNone) {
+            flush_count(t, lkey[e], lval[e]);
+            lkey[e] = kNone;
+            lval[e] = 0u;
+        }
+    }
+    if (threadIdx.x == 0) *fill = 0u;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------- first round
 // Counts every batch point in its leaf.  All leaves are open in this round;
 // a leaf's total is its stored points plus this counter.
 __global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* batch, u32 n) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
+    __shared__ u32 lfill;
     Counters* ctr = t.ctr;
     if (wg_skip(ctr, nullptr)) return;
     for (u32 i = threadIdx.x; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
     }
+    if (threadIdx.x == 0) lfill = 0u;
     __syncthreads();
     const u32 step = gridDim.x * kWG;
     for (u32 base = xcd_block() * kWG; base < n; base += step) {
@@ -184,12 +217,13 @@ __global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* ba
         }
         const Run r = lane_runs(leaf);
         if (leaf != kNone && r.rank == 0u) {
-            const u32 e = lds_find_or_insert(lkey, kLdsBits, leaf);
+            const u32 e = lds_find_or_insert(lkey, kLdsBits, leaf, kCountProbe, &lfill);
             if (e != kNone)
                 atomicAdd(&lval[e], r.len);
             else
                 count_leaf_global(t, leaf, r.len);
         }
+        count_table_tile_end(t, lkey, lval, &lfill);
     }
     __syncthreads();
     for (u32 e = threadIdx.x; e < kLds; e += kWG)
@@ -291,6 +325,7 @@ __global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batc
                                                     u32 base_key, u32 round) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
+    __shared__ u32 lfill;
     Counters* ctr = t.ctr;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->pending_count[round & 1u] = 0u;
     if (wg_skip(ctr, &ctr->pending_count[(round - 1u) & 1u])) return;
@@ -298,6 +333,7 @@ __global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batc
         lkey[i] = kNone;
         lval[i] = 0u;
     }
+    if (threadIdx.x == 0) lfill = 0u;
     __syncthreads();
     const u32 S = ctr->spill_count;
     const u32 nwork = S + n;
@@ -324,13 +360,14 @@ __global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batc
                                   rel_index(t.K, depth, lv, qx, qy, qz));
             const Run r = lane_runs(key);
             if (key != kNone && r.rank == 0u) {
-                const u32 e = lds_find_or_insert(lkey, kLdsBits, key);
+                const u32 e = lds_find_or_insert(lkey, kLdsBits, key, kCountProbe, &lfill);
                 if (e != kNone)
                     atomicAdd(&lval[e], r.len);
                 else
                     flush_count(t, key, r.len);
             }
         }
+        count_table_tile_end(t, lkey, lval, &lfill);
     }
     __syncthreads();
     for (u32 e = threadIdx.x; e < kLds; e += kWG)
@@ -678,7 +715,7 @@ constexpr u32 kCands = 1u << kCandBits;
 // node's new-voxel count is summed in LDS.
 __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 node, u32 stripe,
                                             u32* s_claims, u32* s_nclaims, u32* s_vkey,
-                                            u32* s_vcnt) {
+                                            u32* s_vcnt, u32* s_vfill) {
     const u32 off = atomicAdd(s_nclaims, 1u);
     if (off < kClaimBuf) {
         s_claims[off] = hslot;
@@ -689,7 +726,7 @@ __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 nod
         else
             set_status(t, SIMLOD_OVF_BACKLOG);
     }
-    const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node);
+    const u32 e = lds_find_or_insert(s_vkey, kNodeBits, node, kCountProbe, s_vfill);
     if (e != kNone) {
         atomicAdd(&s_vcnt[e], 1u);
     } else if (atomicAdd(&t.newv[node], 1u) == 0u) {
@@ -726,7 +763,7 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
                                                  u32 rgba, u32 lane, u64* ctag, u64* cval,
                                                  u32 stripe, u32* s_claims, u32* s_nclaims,
-                                                 u32* s_vkey, u32* s_vcnt) {
+                                                 u32* s_vkey, u32* s_vcnt, u32* s_vfill) {
     u64 tag = kEmptyTag;
     if (inner) {
         const u32 lin = cell_lin(qx, qy, qz, t.Dmax - d, t.r, t.R - 1u);
@@ -740,7 +777,7 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     if (cand && !cand_insert(ctag, cval, tag, val)) {  // table full: claim right away
         u32 hslot;
         if (claim_cell(t, tag, val, hslot))
-            stage_claim(t, hslot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt);
+            stage_claim(t, hslot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt, s_vfill);
     }
 }
 
@@ -774,7 +811,7 @@ __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cv
 
 __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch& b, u32 stripe,
                                               u32* s_claims, u32* s_nclaims, u32* s_vkey,
-                                              u32* s_vcnt) {
+                                              u32* s_vcnt, u32* s_vfill) {
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k) {
         if (b.tg[k] == kEmptyTag) continue;
@@ -788,8 +825,50 @@ __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch
         }
         if (fresh)
             stage_claim(t, hslot, (u32)(b.tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey,
-                        s_vcnt);
+                        s_vcnt, s_vfill);
     }
+}
+
+constexpr u32 kClaimFlushAt = kClaimBuf - kCands - kWG;  // room for one more tile
+constexpr u32 kNodeFlushAt = (1u << kNodeBits) / 2u;
+
+// Appends the workgroup's staged claims to its stripe's list (one atomic)
+// and adds its per-node new-voxel counts to the nodes (listing each node the
+// first time); leaves the LDS buffers empty.  Whole workgroup.
+__device__ void flush_staged(const DevTree& t, u32 stripe, u32* s_claims, u32* s_nclaims,
+                             u32* s_vkey, u32* s_vcnt, u32* s_vfill, u32* s_flush) {
+    Counters* ctr = t.ctr;
+    const u32 tid = threadIdx.x;
+    __syncthreads();
+    const u32 nc = min(*s_nclaims, kClaimBuf);
+    if (tid == 0) *s_flush = nc ? atomicAdd(&ctr->claim_count[stripe], nc) : 0u;
+    __syncthreads();
+    u32* dst = t.claims + (u64)stripe * t.claim_cap;
+    for (u32 i = tid; i < nc; i += kWG) {
+        const u32 pos = *s_flush + i;
+        if (pos < t.claim_cap)
+            dst[pos] = s_claims[i];
+        else
+            set_status(t, SIMLOD_OVF_BACKLOG);
+    }
+    for (u32 i = tid; i < (1u << kNodeBits); i += kWG) {
+        const u32 node = s_vkey[i];
+        if (node != kNone && atomicAdd(&t.newv[node], s_vcnt[i]) == 0u) {
+            const u32 p = atomicAdd(&ctr->vtouched_count, 1u);
+            if (p < t.max_nodes)
+                t.vtouched[p] = node;
+            else
+                set_status(t, SIMLOD_OVF_WORK);
+        }
+        s_vkey[i] = kNone;
+        s_vcnt[i] = 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        *s_nclaims = 0u;
+        *s_vfill = 0u;
+    }
+    __syncthreads();
 }
 
 // Walks each point of W once more from the root.  At every inner node it
@@ -812,7 +891,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
     __shared__ u64 s_ctag[kCands], s_cval[kCands];
-    __shared__ u32 s_nclaims, s_flush;
+    __shared__ u32 s_nclaims, s_flush, s_vfill;
     Counters* ctr = t.ctr;
     if (wg_skip(ctr, nullptr)) return;
     const u32 tid = threadIdx.x;
@@ -828,7 +907,10 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         s_vkey[i] = kNone;
         s_vcnt[i] = 0u;
     }
-    if (tid == 0) s_nclaims = 0u;
+    if (tid == 0) {
+        s_nclaims = 0u;
+        s_vfill = 0u;
+    }
     __syncthreads();
 
     const u32 S = ctr->spill_count;
@@ -879,7 +961,8 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
                 desc = false;
             }
             level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w, lane,
-                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
+                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt,
+                             &s_vfill);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
@@ -895,7 +978,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
             level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, lane, s_ctag,
-                             s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
+                             s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
             if (inner) node = c + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
@@ -922,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         }
         if (base + step + tid < nwork)
             fetch_work(t, batch, S, base_key, base + step + tid, rec_n, key_n);
-        claim_resolve(t, cb, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt);
+        claim_resolve(t, cb, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         __syncthreads();
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
@@ -936,30 +1019,14 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
                 set_status(t, SIMLOD_OVF_ARENA);
             }
         }
+        // Staged claims and node counts go out before the buffers can
+        // overflow in the next tile.  The decision is read by every thread
+        // before the barrier and changed by none until after it: uniform.
+        const bool flush = s_nclaims > kClaimFlushAt || s_vfill >= kNodeFlushAt;
+        __syncthreads();
+        if (flush) flush_staged(t, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill, &s_flush);
     }
-    __syncthreads();
-    // flush staged claims (one atomic per workgroup) and per-node counts
-    const u32 nc = min(s_nclaims, kClaimBuf);
-    if (tid == 0) s_flush = nc ? atomicAdd(&ctr->claim_count[stripe], nc) : 0u;
-    __syncthreads();
-    u32* dst = t.claims + (u64)stripe * t.claim_cap;
-    for (u32 i = tid; i < nc; i += kWG) {
-        const u32 pos = s_flush + i;
-        if (pos < t.claim_cap)
-            dst[pos] = s_claims[i];
-        else
-            set_status(t, SIMLOD_OVF_BACKLOG);
-    }
-    for (u32 i = tid; i < (1u << kNodeBits); i += kWG) {
-        const u32 node = s_vkey[i];
-        if (node != kNone && atomicAdd(&t.newv[node], s_vcnt[i]) == 0u) {
-            const u32 p = atomicAdd(&ctr->vtouched_count, 1u);
-            if (p < t.max_nodes)
-                t.vtouched[p] = node;
-            else
-                set_status(t, SIMLOD_OVF_WORK);
-        }
-    }
+    flush_staged(t, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill, &s_flush);
 }
 
 // ------------------------------------------------------- voxel stores
