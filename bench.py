@@ -108,6 +108,220 @@ def generate(name, n=None):
     return pointgen.tiny_planes(n, seed=0)
 
 
+def cloud_config(cloud, batch):
+    """Launch configuration of one cloud of the batched workload, sized to it."""
+    from paper_2310_03567_amd import simlod
+
+    n = len(cloud["points"])
+    return simlod.make_config(
+        root_min=cloud["root_min"], root_size=cloud["root_size"], max_batch=batch,
+        max_nodes=int(min(1 << 21, n // 2000 + 8192)),
+        arena_bytes=int(48 * n + (n // 20_000) * (256 << 10) + (128 << 20)),
+        spill_capacity=int(max(1 << 20, 4 * batch)), backlog_capacity=int(max(1 << 20, 2 * batch)),
+        hist_capacity=int(min(8192, max(256, n // 20_000))))
+
+
+def run_batched(args):
+    """64 independent clouds of uneven size (log-uniform 100k..50M points,
+    aerial heightfields and dense building scans), each cut into 10 batches;
+    step s inserts batch s of every cloud.  The group form inserts a step in
+    one pass over all clouds (autotuned launch shape, replayed hipGraph);
+    the plain form inserts each cloud's batch with its own call, in turn, on
+    the same stream.  Both start from empty octrees and insert the same
+    points; the octrees must come out identical."""
+    import torch
+
+    import pointgen
+    from paper_2310_03567_amd import simlod
+
+    t0 = time.perf_counter()
+    clouds = pointgen.cloud_set(count=64, seed=3)
+    total = sum(len(c["points"]) for c in clouds)
+    log(f"generated {len(clouds)} clouds, {total} points in {time.perf_counter() - t0:.1f} s")
+    steps = 10
+    devs, cuts = [], []
+    for c in clouds:
+        p = c["points"]
+        devs.append(torch.from_numpy(p.view(np.uint8).reshape(-1)).to("cuda:0"))
+        cuts.append(np.linspace(0, len(p), steps + 1).astype(np.int64))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def batch_of(i, k):
+        return devs[i][int(cuts[i][k]) * 16:int(cuts[i][k + 1]) * 16]
+
+    trees = [simlod.Octree(cloud_config(c, int(cuts[i][1] - cuts[i][0]) + 1))
+             for i, c in enumerate(clouds)]
+
+    def timed_run(insert_step):
+        for t in trees:
+            t.reset(stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            insert_step(k)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t_start
+        return el, np.array([a.elapsed_time(b) for a, b in ev])
+
+    def plain_step(k):
+        for i, t in enumerate(trees):
+            t.insert(batch_of(i, k), stream)
+
+    group = simlod.Group(trees, graph=True, autotune=True)
+
+    def group_step(k):
+        group.insert([batch_of(i, k) for i in range(len(trees))], stream)
+
+    # warmup: the group's tuning passes and graph capture, then the plain form
+    for _ in range(max(1, -(-simlod.TUNE_PASSES // steps))):
+        timed_run(group_step)
+    timed_run(plain_step)
+    el_plain, lat_plain = timed_run(plain_step)
+    plain_canon = [t.snapshot(nodes_only=True).nodes.tobytes() for t in trees[:8]]
+    el_group, lat_group = timed_run(group_step)
+    group.sync()
+    shape = group.shape()
+    same = all(t.snapshot(nodes_only=True).nodes.tobytes() == c
+               for t, c in zip(trees[:8], plain_canon))
+    st = [t.stats() for t in trees]
+    group.close()
+    for t in trees:
+        t.close()
+    value = total / el_group
+    result = {
+        "metric": "inserted points/sec, 64 clouds per step (batched group form)",
+        "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": steps,
+        "warmup": steps, "ms_per_step": round(el_group * 1e3 / steps, 4),
+        "step_ms_p50": round(float(np.percentile(lat_group, 50)), 4),
+        "step_ms_p99": round(float(np.percentile(lat_group, 99)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 clouds, log-uniform 100k..50M points, aerial or dense-scan "
+                               "by seed, 10 batches each", "points": total, "clouds": 64},
+        "plain_form": {"value": round(total / el_plain, 1), "unit": "points/s",
+                       "ms_per_step": round(el_plain * 1e3 / steps, 4),
+                       "step_ms_p50": round(float(np.percentile(lat_plain, 50)), 4),
+                       "step_ms_p99": round(float(np.percentile(lat_plain, 99)), 4)},
+        "speedup_vs_plain": round(el_plain / el_group, 3),
+        "group_shape": shape,
+        "node_tables_identical": bool(same),
+        "status_ok": all(x["status_bits"] == 0 for x in st),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def run_served(args):
+    """Continuous batching under load.  16 stream slots serve 20 clouds of
+    10M..200M points (log-uniform; aerial or dense scan by seed), each cut
+    into requests of 50k..5M points (log-uniform); requests of a slot arrive
+    as a Poisson process.  A finished cloud's octree is closed (after its
+    last request) and the slot admits the next cloud against a 200 GB
+    device-memory budget.  The same arrival trace is served twice: batched
+    (every pass takes the oldest request of each stream) and unbatched (one
+    request per pass, arrival order).  Latency = submission to completion."""
+    import torch
+
+    import pointgen
+    from paper_2310_03567_amd import simlod
+
+    t0 = time.perf_counter()
+    clouds = pointgen.cloud_set(count=20, seed=4, lo=1e7, hi=2e8)
+    total = sum(len(c["points"]) for c in clouds)
+    log(f"generated {len(clouds)} clouds, {total} points in {time.perf_counter() - t0:.1f} s")
+    devs = [torch.from_numpy(c["points"].view(np.uint8).reshape(-1)).to("cuda:0") for c in clouds]
+    torch.cuda.synchronize()
+    reqs = []
+    for i, c in enumerate(clouds):
+        rng = np.random.default_rng(4000 + i)
+        n, a, cuts = len(c["points"]), 0, [0]
+        while a < n:
+            a = min(n, a + int(np.exp(rng.uniform(np.log(5e4), np.log(5e6)))))
+            cuts.append(a)
+        reqs.append(cuts)
+    nreq = sum(len(r) - 1 for r in reqs)
+    mean_req = total / nreq
+    slots = 16
+    cfgs = [cloud_config(c, 5_000_000) for c in clouds]
+
+    def serve(offered_pps, max_per_pass, seed):
+        rate = offered_pps / slots / mean_req  # requests/s per slot
+        rng = np.random.default_rng(seed)
+        lat, pending = [], []
+        with simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=max_per_pass) as sv:
+            queue = list(range(len(clouds)))
+            active = {}  # slot index -> [cloud, next request, stream id, next arrival, tickets]
+            start = time.perf_counter()
+            for k in range(slots):
+                active[k] = None
+            done_points = 0
+            while True:
+                now = time.perf_counter() - start
+                for k in range(slots):
+                    st = active[k]
+                    if st is None and queue:
+                        sid = sv.open(cfgs[queue[0]])
+                        if sid is not None:
+                            ci = queue.pop(0)
+                            active[k] = [ci, 0, sid, now + rng.exponential(1.0 / rate), []]
+                        continue
+                    if st is None:
+                        continue
+                    ci, r, sid, t_next, tickets = st
+                    cuts = reqs[ci]
+                    while r < len(cuts) - 1 and t_next <= now:
+                        b = devs[ci][cuts[r] * 16:cuts[r + 1] * 16]
+                        tickets.append(sv.submit(sid, b))
+                        r += 1
+                        t_next += rng.exponential(1.0 / rate)
+                    st[1], st[3] = r, t_next
+                    if r == len(cuts) - 1 and all(sv.poll(t)[0] for t in tickets[-1:]):
+                        for t in tickets:
+                            d, ms, rc = sv.poll(t)
+                            if not d or rc != simlod.OK:
+                                raise RuntimeError(f"request failed ({rc})")
+                            lat.append(ms)
+                        done_points += cuts[-1]
+                        sv.close_stream(sid)
+                        active[k] = None
+                if not queue and all(v is None for v in active.values()):
+                    break
+                time.sleep(0.0002)
+            el = time.perf_counter() - start
+            c = sv.counters()
+        lat = np.array(lat)
+        return {"offered_points_per_s": round(offered_pps, 1),
+                "achieved_points_per_s": round(done_points / el, 1),
+                "requests": int(len(lat)), "passes": int(c["passes"]),
+                "requests_per_pass": round(len(lat) / max(c["passes"], 1), 2),
+                "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                "seconds": round(el, 3)}
+
+    offered = args.offered * 1e9
+    serve(offered, 0, seed=40)  # warm-up run
+    batched = serve(offered, 0, seed=41)
+    plain = serve(offered, 1, seed=41)
+    result = {
+        "metric": "served insertion: points/sec with p50/p99 update latency",
+        "value": batched["achieved_points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "steps": batched["requests"], "warmup": 1,
+        "ms_per_step": round(batched["seconds"] * 1e3 / max(batched["requests"], 1), 4),
+        "update_ms_p50": batched["latency_ms_p50"], "update_ms_p99": batched["latency_ms_p99"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16 stream slots, 20 clouds of 10M..200M points, requests of "
+                               "50k..5M points, Poisson arrivals, 200 GB admission budget",
+                   "points": total, "requests": nreq},
+        "batched": batched, "unbatched": plain,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def cpu_baseline(points, batch, cfg_kw, budget_s=20.0):
     """Sequential C oracle (one thread) on a prefix of the same batches."""
     from oracle import LodConfig
@@ -132,7 +346,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="aerial", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="aerial",
+                    choices=sorted(WORKLOADS) + ["batched", "served"])
+    ap.add_argument("--offered", type=float, default=1.5,
+                    help="served workload: offered load in G points/s over all streams")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -143,6 +360,13 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(nothing in this build uses a second GPU)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        run_batched(args)
+        return
+    if args.workload == "served":
+        run_served(args)
+        return
 
     import torch
 

@@ -63,6 +63,7 @@ extern "C" {
 #define SIMLOD_ERR_POISONED (-5)         /* handle unusable after an earlier error */
 #define SIMLOD_ERR_KEY_SPACE (-6)        /* more than 2^32 - 1 points in one octree */
 #define SIMLOD_ERR_NOT_FOUND (-7)        /* simlod_snapshot_subtree: no node with that path */
+#define SIMLOD_ERR_BUSY (-8)             /* server: no stream slot or HBM budget free now */
 
 /* Bits of simlod_stats_data.status_bits (device-side overflow causes). */
 #define SIMLOD_OVF_NODES 0x1u   /* node table (max_nodes) full            */
@@ -270,6 +271,142 @@ int simlod_set_kernel_timing(simlod_octree* h, uint32_t kernel_mask);
 
 /* Synchronizes and returns the times accumulated since timing was enabled. */
 int simlod_get_kernel_times(simlod_octree* h, simlod_kernel_times* out);
+
+/* ---------------------------------------------------------------------
+ * Batched insertion: one pass over a group of octrees.
+ *
+ * A group inserts one batch into each of up to SIMLOD_MAX_GROUP octrees
+ * (all on one device) with a single sequence of kernel launches whose work
+ * is the members' batches together: small batches of many clouds fill the
+ * GPU as one large batch does (the paper inserts one cloud's batches in
+ * turn, section "Incrementally Updating the Octree").  Each member's octree
+ * is exactly the one its own simlod_insert_batch calls would give.
+ * --------------------------------------------------------------------- */
+#define SIMLOD_MAX_GROUP 128
+
+typedef struct simlod_group simlod_group;
+
+#define SIMLOD_GROUP_GRAPH 0x1u    /* replay passes from one captured hipGraph */
+#define SIMLOD_GROUP_AUTOTUNE 0x2u /* tune the launch shape on the first passes */
+
+/* Creates a group over `count` distinct handles of one device (the handles
+ * stay owned by the caller and must outlive the group; while the group is
+ * in use a member must not be inserted into through another call at the
+ * same time).  flags: SIMLOD_GROUP_*.
+ * With SIMLOD_GROUP_AUTOTUNE the first SIMLOD_TUNE_PASSES passes try
+ * candidate workgroup counts for the point-parallel kernels (timed with HIP
+ * events, which synchronizes those passes), then keep the fastest per
+ * kernel.  With SIMLOD_GROUP_GRAPH, once the shape is settled, the pass is
+ * captured into a hipGraph on first use and later passes replay it with
+ * only the first kernel's arguments changed.
+ * Errors: INVALID_ARGUMENT (NULL, count 0 or > SIMLOD_MAX_GROUP, repeated
+ * or poisoned handles, mixed devices), OUT_OF_MEMORY, HIP. */
+int simlod_group_create(simlod_octree* const* members, uint32_t count, uint32_t flags,
+                        simlod_group** out);
+
+/* Inserts pts[i][0..n[i]) into member i for every i (n[i] may be 0).  Every
+ * pts[i] with n[i] > 0 must be 16-byte-aligned device memory.  Members'
+ * batches larger than their max_batch are cut into several passes.
+ * Enqueued on `stream`; returns after enqueueing.
+ * Errors: INVALID_ARGUMENT, KEY_SPACE (some member would pass 2^32 - 1
+ * points; nothing is enqueued), POISONED (a member is), CAPACITY (a member
+ * overflowed in an earlier group pass; it is now poisoned), HIP. */
+int simlod_group_insert(simlod_group* g, const simlod_point* const* pts, const uint64_t* n,
+                        void* stream);
+
+#define SIMLOD_TUNE_PASSES 10
+
+/* The launch shape in use: the largest workgroup count of the point
+ * counting, histogram counting, sampling/store and voxel-store kernels, and
+ * whether tuning has finished (1) and a graph is captured (bit 1). */
+int simlod_group_shape(simlod_group* g, uint32_t caps[4], uint32_t* state);
+
+/* Times passes of the group per kernel (as simlod_set_kernel_timing). */
+int simlod_group_set_kernel_timing(simlod_group* g, uint32_t kernel_mask);
+int simlod_group_get_kernel_times(simlod_group* g, simlod_kernel_times* out);
+
+/* Waits for the group's passes; reports members' device-side errors. */
+int simlod_group_sync(simlod_group* g);
+
+/* Releases the group (not its members); NULL is a no-op. */
+int simlod_group_destroy(simlod_group* g);
+
+/* Chunk-capacity autotuner: inserts the sample (device memory, 16-byte
+ * aligned) into a scratch octree built from *cfg with each candidate
+ * chunk_capacity in turn, timing the passes with HIP events on `stream`,
+ * and returns the fastest candidate in *best (and its time in *best_ms, if
+ * not NULL).  The chunk size changes memory layout and speed, never the
+ * canonical octree (section "Chunks and the Chunk Pool" measures the
+ * trade-off).  Scratch octrees are created and destroyed one at a time.
+ * Errors: as simlod_create and simlod_insert_batch. */
+int simlod_tune_chunk_capacity(const simlod_config* cfg, const simlod_point* sample, uint64_t n,
+                               const uint32_t* candidates, uint32_t count, void* stream,
+                               uint32_t* best, double* best_ms);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of insertion requests.
+ *
+ * A server keeps the octrees of its open streams resident on one device and
+ * runs a request loop on its own host threads.  Each pass takes the oldest
+ * queued request of every stream that has one and inserts them together
+ * (one group pass, see simlod_group_insert), so requests that arrive while
+ * others are on the GPU join the next pass; up to two passes are in flight,
+ * so the device does not idle while requests wait.  A stream's requests are
+ * applied in submission order, so each octree is exactly what inserting its
+ * requests alone, in order, gives (the paper streams batches of one cloud
+ * into one octree, section "Incrementally Updating the Octree").
+ * --------------------------------------------------------------------- */
+typedef struct simlod_server simlod_server;
+
+typedef struct simlod_server_config {
+    int device;
+    uint32_t max_streams;       /* open octrees at once, 1..SIMLOD_MAX_GROUP */
+    uint64_t hbm_budget;        /* device bytes the open octrees may hold */
+    uint32_t max_per_pass;      /* requests per pass (0 = one per stream);
+                                   1 serves requests one at a time, in
+                                   arrival order: the unbatched form */
+    uint32_t reserved;
+} simlod_server_config;
+
+int simlod_server_create(const simlod_server_config* cfg, simlod_server** out);
+
+/* Device bytes simlod_create allocates for *cfg (arena_bytes must be set:
+ * a served octree cannot take "90% of free memory"). */
+int simlod_config_device_bytes(const simlod_config* cfg, uint64_t* bytes);
+
+/* Admits an octree with configuration *cfg (its device must be the
+ * server's): BUSY when no stream slot is free or its device bytes would
+ * exceed the budget left; *id names the stream. */
+int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id);
+
+/* Queues the insertion of pts[0..n) (16-byte-aligned device memory that the
+ * caller keeps valid until the request completes) into stream id.
+ * *ticket identifies the request.  Returns at once.
+ * Errors: INVALID_ARGUMENT, KEY_SPACE, POISONED (the stream's octree is). */
+int simlod_server_submit(simlod_server* sv, uint32_t id, const simlod_point* pts, uint64_t n,
+                         uint64_t* ticket);
+
+/* State of a request: *done = 1 once its pass has completed; *latency_ms
+ * (may be NULL) = completion - submission, host clock.  Returns the
+ * request's own status: CAPACITY if its stream overflowed. */
+int simlod_server_poll(simlod_server* sv, uint64_t ticket, int* done, double* latency_ms);
+
+/* Blocks until every request submitted so far has completed. */
+int simlod_server_drain(simlod_server* sv);
+
+/* The stream's octree handle, for snapshots and stats once its requests
+ * have completed (owned by the server; NULL if id is not open). */
+simlod_octree* simlod_server_octree(simlod_server* sv, uint32_t id);
+
+/* Waits for the stream's requests, destroys its octree, frees its budget. */
+int simlod_server_close(simlod_server* sv, uint32_t id);
+
+/* Counters: passes launched, requests completed, points inserted, device
+ * bytes held by open octrees. */
+int simlod_server_counters(simlod_server* sv, uint64_t out[4]);
+
+/* Stops the loop, closes every stream; NULL is a no-op. */
+int simlod_server_destroy(simlod_server* sv);
 
 /* Static description of a status code. */
 const char* simlod_status_string(int code);

@@ -3,9 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -17,9 +21,23 @@
 
 using namespace simlod;
 
+// Per-kernel HIP-event timing of the passes a handle or group enqueues.
+struct Timing {
+    uint32_t mask = 0;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    simlod_kernel_times acc;
+};
+
 struct simlod_octree {
     simlod_config cfg;
     DevTree t;
+    DevTree* d_tree = nullptr;   // device copy of t, read by the kernels
+    Member* d_members = nullptr; // the handle's one-member table for its own passes
     int device = 0;
     u64 hash_entries = 0;
     u64 total_points = 0;
@@ -34,15 +52,10 @@ struct simlod_octree {
     uint4* staging = nullptr;
     u64 staging_cap = 0;
     std::vector<void*> dev_allocs;
-    // kernel timing
-    uint32_t timing_mask = 0;
-    struct Pending {
-        int kind;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> free_events;
-    simlod_kernel_times acc;
+    LaunchShape shape = default_shape();
+    Timing tm;
+    u64 dev_bytes = 0;     // device memory held
+    u64* dry = nullptr;    // set: dalloc only adds up sizes
 };
 
 namespace {
@@ -77,6 +90,12 @@ template <typename T>
 bool dalloc(simlod_octree* h, T** p, u64 count) {
     void* v = nullptr;
     u64 bytes = std::max<u64>(count * sizeof(T), 256);
+    if (h->dry) {  // sizing only
+        *h->dry += bytes;
+        *p = nullptr;
+        return true;
+    }
+    h->dev_bytes += bytes;
     hipError_t e = hipMalloc(&v, bytes);
     if (e != hipSuccess) {
         note_error("hipMalloc", e);
@@ -109,19 +128,23 @@ bool cfg_valid(const simlod_config* c) {
     return true;
 }
 
+void free_timing(Timing& tm) {
+    for (auto& p : tm.pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : tm.free_events) (void)hipEventDestroy(e);
+    tm.pending.clear();
+    tm.free_events.clear();
+}
+
 void free_all(simlod_octree* h) {
     for (void* p : h->dev_allocs) (void)hipFree(p);
     h->dev_allocs.clear();
     if (h->h_status) (void)hipHostFree(h->h_status);
     h->h_status = nullptr;
     if (h->status_ev) (void)hipEventDestroy(h->status_ev);
-    for (auto& p : h->pending) {
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
-    }
-    for (auto e : h->free_events) (void)hipEventDestroy(e);
-    h->pending.clear();
-    h->free_events.clear();
+    free_timing(h->tm);
 }
 
 // Reads the status word copied after the last pass.  wait: block until it
@@ -147,10 +170,10 @@ int poll_status(simlod_octree* h, bool wait) {
     return SIMLOD_OK;
 }
 
-hipEvent_t take_event(simlod_octree* h) {
-    if (!h->free_events.empty()) {
-        hipEvent_t e = h->free_events.back();
-        h->free_events.pop_back();
+hipEvent_t take_event(Timing& tm) {
+    if (!tm.free_events.empty()) {
+        hipEvent_t e = tm.free_events.back();
+        tm.free_events.pop_back();
         return e;
     }
     hipEvent_t e = nullptr;
@@ -159,28 +182,28 @@ hipEvent_t take_event(simlod_octree* h) {
 }
 
 template <typename F>
-hipError_t timed(simlod_octree* h, int kind, hipStream_t s, F&& launch) {
-    if (!((h->timing_mask >> kind) & 1u)) return launch();
-    hipEvent_t a = take_event(h), b = take_event(h);
+hipError_t timed(Timing* tm, int kind, hipStream_t s, F&& launch) {
+    if (!tm || !((tm->mask >> kind) & 1u)) return launch();
+    hipEvent_t a = take_event(*tm), b = take_event(*tm);
     (void)hipEventRecord(a, s);
     hipError_t e = launch();
     (void)hipEventRecord(b, s);
-    h->pending.push_back({kind, a, b});
+    tm->pending.push_back({kind, a, b});
     return e;
 }
 
-void drain_timing(simlod_octree* h) {
-    for (auto& p : h->pending) {
+void drain_timing(Timing& tm) {
+    for (auto& p : tm.pending) {
         float ms = 0.f;
         (void)hipEventSynchronize(p.b);
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-            h->acc.launches[p.kind] += 1;
-            h->acc.total_ms[p.kind] += ms;
+            tm.acc.launches[p.kind] += 1;
+            tm.acc.total_ms[p.kind] += ms;
         }
-        h->free_events.push_back(p.a);
-        h->free_events.push_back(p.b);
+        tm.free_events.push_back(p.a);
+        tm.free_events.push_back(p.b);
     }
-    h->pending.clear();
+    tm.pending.clear();
 }
 
 bool is_device_ptr(const void* p) {
@@ -194,30 +217,49 @@ bool is_device_ptr(const void* p) {
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-// One insertion pass over n <= max_batch device-resident points.
-hipError_t enqueue_pass(simlod_octree* h, const uint4* batch, u32 n, u32 base_key, hipStream_t s) {
-    const DevTree& t = h->t;
-    const u32 rounds = expansion_rounds(h->cfg.max_depth);
-    hipError_t e = timed(h, SIMLOD_KERNEL_COUNT, s, [&] { return launch_count_leaves(t, batch, n, s); });
+// One insertion pass over a group of octrees, each member's share of at most
+// its max_batch device-resident points (a single octree is a group of one).
+// items: batch points summed over the members (for a captured pass: their
+// capacity); rounds: the largest member's expansion rounds; tm: timing (may
+// be null); status_out: per-member status words (may be null).
+hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const LaunchShape& sh,
+                              Timing* tm, u32* status_out, hipStream_t s) {
+    const Member* M = ga.table;
+    const u32 cnt = ga.count;
+    hipError_t e = timed(tm, SIMLOD_KERNEL_COUNT, s,
+                         [&] { return launch_count_leaves(ga, items, sh, s); });
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(t, n, s); });
+        e = timed(tm, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(M, cnt, items, s); });
     for (u32 k = 2; k <= rounds && e == hipSuccess; ++k) {
-        e = timed(h, SIMLOD_KERNEL_COUNT_HIST, s,
-                  [&] { return launch_count_hist(t, batch, n, base_key, k, s); });
+        e = timed(tm, SIMLOD_KERNEL_COUNT_HIST, s,
+                  [&] { return launch_count_hist(M, cnt, items, k, sh, s); });
         if (e == hipSuccess)
-            e = timed(h, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(t, k, s); });
+            e = timed(tm, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(M, cnt, k, s); });
     }
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(t, 0u, s); });
+        e = timed(tm, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(M, cnt, 0u, s); });
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_SAMPLE_STORE, s,
-                  [&] { return launch_sample_store(t, batch, n, base_key, s); });
+        e = timed(tm, SIMLOD_KERNEL_SAMPLE_STORE, s,
+                  [&] { return launch_sample_store(M, cnt, items, sh, s); });
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_ALLOC_VOXELS, s, [&] { return launch_alloc(t, 1u, s); });
+        e = timed(tm, SIMLOD_KERNEL_ALLOC_VOXELS, s, [&] { return launch_alloc(M, cnt, 1u, s); });
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_STORE_VOXELS, s, [&] { return launch_store_voxels(t, n, s); });
+        e = timed(tm, SIMLOD_KERNEL_STORE_VOXELS, s,
+                  [&] { return launch_store_voxels(M, cnt, items, sh, s); });
     if (e == hipSuccess)
-        e = timed(h, SIMLOD_KERNEL_FINISH, s, [&] { return launch_finish(t, s); });
+        e = timed(tm, SIMLOD_KERNEL_FINISH, s,
+                  [&] { return launch_finish(M, cnt, status_out, s); });
+    return e;
+}
+
+// One pass of a single handle over n <= max_batch device-resident points.
+hipError_t enqueue_pass(simlod_octree* h, const uint4* batch, u32 n, u32 base_key, hipStream_t s) {
+    GroupArgs ga{};
+    ga.table = h->d_members;
+    ga.count = 1;
+    ga.m[0] = Member{h->d_tree, batch, n, base_key};
+    hipError_t e = enqueue_group_pass(ga, n, expansion_rounds(h->cfg.max_depth), h->shape, &h->tm,
+                                      nullptr, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->h_status, &h->t.ctr->status, sizeof(u32), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(h->status_ev, s);
@@ -260,10 +302,70 @@ int sync_handle(simlod_octree* h) {
         h->sticky = SIMLOD_ERR_HIP;
         return SIMLOD_ERR_HIP;
     }
-    return poll_status(h, true);
+    const int rc = poll_status(h, true);
+    if (rc) return rc;
+    // group passes leave no host copy of the status word: read it
+    u32 st = 0;
+    if (hipMemcpy(&st, &h->t.ctr->status, sizeof(u32), hipMemcpyDeviceToHost) != hipSuccess) {
+        note_error("status read", hipGetLastError());
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    if (st) {
+        h->poisoned = 1;
+        h->sticky = SIMLOD_ERR_CAPACITY;
+        return SIMLOD_ERR_CAPACITY;
+    }
+    return SIMLOD_OK;
 }
 
 }  // namespace
+
+// Every device buffer of an octree (the same sequence sizes a configuration
+// when h->dry is set).  arena_bytes: 0 = 90% of the free memory.
+static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_bytes) {
+    DevTree& t = h->t;
+    std::memset(&t, 0, sizeof(t));
+    const u64 N = cfg->max_nodes;
+    const u64 work = cfg->max_batch + cfg->spill_capacity;
+    h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
+    t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
+    const u32 hist_slots = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
+    bool ok = dalloc(h, &t.child, N) && dalloc(h, &t.count, N) && dalloc(h, &t.cnt, N) &&
+              dalloc(h, &t.hslot, N) && dalloc(h, &t.geo, N) && dalloc(h, &t.grid, N) &&
+              dalloc(h, &t.tab, N) && dalloc(h, &t.tabcap, N) && dalloc(h, &t.nchunks, N) &&
+              dalloc(h, &t.newv, N) && dalloc(h, &t.ctr, 1) &&
+              dalloc(h, &t.dir, dir_offset(t.dir_depth + 1u)) &&
+              dalloc(h, &t.spill_rec, cfg->spill_capacity) &&
+              dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched, N) &&
+              dalloc(h, &t.pending[0], N) && dalloc(h, &t.pending[1], N) &&
+              dalloc(h, &t.zero_list, N) &&
+              dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
+              dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
+              dalloc(h, &t.amask[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
+              dalloc(h, &t.hval, h->hash_entries) &&
+              dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
+              dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 1);
+    const u32 C = cfg->chunk_capacity;
+    const u64 chunk_bytes = (u64)C * 20u + 4u;
+    t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);
+    const u64 cells = 1ull << (3 * cfg->grid_bits);
+    t.grid_words = (u32)std::max<u64>(1, cells / 32);
+    t.grid_blocks = (u32)((t.grid_words * 4ull + kBlockBytes - 1) / kBlockBytes);
+    if (arena_bytes == 0) arena_bytes = cfg->arena_bytes;
+    if (ok && arena_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) ok = false;
+        // pool entries need 4 bytes per chunk of the arena as well
+        arena_bytes = (u64)((double)fr * 0.9 * (double)chunk_bytes / (double)(chunk_bytes + 4));
+    }
+    u64 blocks = std::min<u64>(arena_bytes / kBlockBytes, 0xFFFFFFF0ull);
+    t.arena_blocks = (u32)blocks;
+    t.pool_cap = t.arena_blocks / t.chunk_blocks + 1;
+    ok = ok && blocks > 0 && dalloc(h, &t.arena, blocks * (u64)kBlockBytes) &&
+         dalloc(h, &t.pool, t.pool_cap);
+    return ok;
+}
 
 extern "C" {
 
@@ -302,46 +404,8 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     if (!h) return SIMLOD_ERR_OUT_OF_MEMORY;
     h->cfg = *cfg;
     h->device = cfg->device;
-    std::memset(&h->acc, 0, sizeof(h->acc));
-    DevTree& t = h->t;
-    std::memset(&t, 0, sizeof(t));
-    const u64 N = cfg->max_nodes;
-    const u64 work = cfg->max_batch + cfg->spill_capacity;
-    h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
-    t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
-    const u32 hist_slots = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
-    bool ok = dalloc(h, &t.child, N) && dalloc(h, &t.count, N) && dalloc(h, &t.cnt, N) &&
-              dalloc(h, &t.hslot, N) && dalloc(h, &t.geo, N) && dalloc(h, &t.grid, N) &&
-              dalloc(h, &t.tab, N) && dalloc(h, &t.tabcap, N) && dalloc(h, &t.nchunks, N) &&
-              dalloc(h, &t.newv, N) && dalloc(h, &t.ctr, 1) &&
-              dalloc(h, &t.dir, dir_offset(t.dir_depth + 1u)) &&
-              dalloc(h, &t.spill_rec, cfg->spill_capacity) &&
-              dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched, N) &&
-              dalloc(h, &t.pending[0], N) && dalloc(h, &t.pending[1], N) &&
-              dalloc(h, &t.zero_list, N) &&
-              dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
-              dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
-              dalloc(h, &t.amask[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
-              dalloc(h, &t.hval, h->hash_entries) &&
-              dalloc(h, &t.claims, cfg->backlog_capacity * kStripes);
-    const u32 C = cfg->chunk_capacity;
-    const u64 chunk_bytes = (u64)C * 20u + 4u;
-    t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);
-    const u64 cells = 1ull << (3 * cfg->grid_bits);
-    t.grid_words = (u32)std::max<u64>(1, cells / 32);
-    t.grid_blocks = (u32)((t.grid_words * 4ull + kBlockBytes - 1) / kBlockBytes);
-    u64 arena_bytes = cfg->arena_bytes;
-    if (ok && arena_bytes == 0) {
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) ok = false;
-        // pool entries need 4 bytes per chunk of the arena as well
-        arena_bytes = (u64)((double)fr * 0.9 * (double)chunk_bytes / (double)(chunk_bytes + 4));
-    }
-    u64 blocks = std::min<u64>(arena_bytes / kBlockBytes, 0xFFFFFFF0ull);
-    t.arena_blocks = (u32)blocks;
-    t.pool_cap = t.arena_blocks / t.chunk_blocks + 1;
-    ok = ok && blocks > 0 && dalloc(h, &t.arena, blocks * (u64)kBlockBytes) &&
-         dalloc(h, &t.pool, t.pool_cap);
+    std::memset(&h->tm.acc, 0, sizeof(h->tm.acc));
+    bool ok = allocate_all(h, cfg, 0);
     if (ok && hipHostMalloc((void**)&h->h_status, sizeof(u32), hipHostMallocDefault) != hipSuccess)
         ok = false;
     if (ok && hipEventCreateWithFlags(&h->status_ev, hipEventDisableTiming) != hipSuccess)
@@ -354,10 +418,11 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
         return SIMLOD_ERR_OUT_OF_MEMORY;
     }
     *h->h_status = 0;
+    DevTree& t = h->t;
     t.max_nodes = cfg->max_nodes;
-    t.hist_cap = hist_slots;
+    t.hist_cap = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
     t.spill_cap = (u32)cfg->spill_capacity;
-    t.active_cap = (u32)work;
+    t.active_cap = (u32)(cfg->max_batch + cfg->spill_capacity);
     t.hmask = (u32)(h->hash_entries - 1);
     t.claim_cap = (u32)cfg->backlog_capacity;
     for (int a = 0; a < 3; ++a) t.mn[a] = cfg->root_min[a];
@@ -367,10 +432,12 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     t.R = 1u << cfg->grid_bits;
     t.Dmax = cfg->max_depth;
     t.T = cfg->leaf_capacity;
-    t.C = C;
+    t.C = cfg->chunk_capacity;
     t.scale = (float)(1u << t.K) / cfg->root_size;  // float32 division
     clear_stale_error();
-    hipError_t re = launch_reset(t, h->hash_entries, nullptr);
+    hipError_t re = hipMemcpy(h->d_tree, &t, sizeof(DevTree), hipMemcpyHostToDevice);
+    if (re != hipSuccess) note_error("device tree copy", re);
+    if (re == hipSuccess) re = launch_reset(t, h->hash_entries, nullptr);
     if (re != hipSuccess) note_error("reset kernels (launch)", re);
     if (re == hipSuccess) {
         re = hipStreamSynchronize(nullptr);
@@ -692,18 +759,790 @@ int simlod_destroy(simlod_octree* h) {
 int simlod_set_kernel_timing(simlod_octree* h, uint32_t kernel_mask) {
     if (!h) return SIMLOD_ERR_INVALID_ARGUMENT;
     DeviceGuard guard(h->device);
-    drain_timing(h);
-    std::memset(&h->acc, 0, sizeof(h->acc));
-    h->timing_mask = kernel_mask & ((1u << SIMLOD_NUM_KERNELS) - 1u);
+    drain_timing(h->tm);
+    std::memset(&h->tm.acc, 0, sizeof(h->tm.acc));
+    h->tm.mask = kernel_mask & ((1u << SIMLOD_NUM_KERNELS) - 1u);
     return SIMLOD_OK;
 }
 
 int simlod_get_kernel_times(simlod_octree* h, simlod_kernel_times* out) {
     if (!h || !out) return SIMLOD_ERR_INVALID_ARGUMENT;
     DeviceGuard guard(h->device);
-    drain_timing(h);
-    *out = h->acc;
+    drain_timing(h->tm);
+    *out = h->tm.acc;
     return SIMLOD_OK;
+}
+
+// ------------------------------------------------------------------ groups
+}  // extern "C"
+
+namespace {
+
+constexpr u32 kTuneCaps[] = {256u, 512u, 1024u, 2048u, 4096u};
+constexpr u32 kTuneCands = sizeof(kTuneCaps) / sizeof(kTuneCaps[0]);
+constexpr int kShapeKernel[kNumShapes] = {SIMLOD_KERNEL_COUNT, SIMLOD_KERNEL_COUNT_HIST,
+                                          SIMLOD_KERNEL_SAMPLE_STORE, SIMLOD_KERNEL_STORE_VOXELS};
+
+}  // namespace
+
+struct simlod_group {
+    std::vector<simlod_octree*> members;
+    int device = 0;
+    uint32_t flags = 0;
+    Member* d_table = nullptr;   // member table the pass's later kernels read
+    u32* d_status = nullptr;     // members' status words after the last pass
+    u32* h_status = nullptr;     // pinned copy
+    hipEvent_t status_ev = nullptr;
+    bool status_pending = false;
+    hipStream_t last_stream = nullptr;
+    u32 rounds = 1;
+    u64 cap_items = 0;           // summed max_batch: the captured pass's launch shape
+    LaunchShape shape = default_shape();
+    Timing tm;
+    // launch-shape tuning
+    Timing tune_tm;
+    u32 tune_pass = 0;
+    bool tuned = false;
+    double tune_cost[kNumShapes][kTuneCands] = {};
+    // graph replay
+    hipStream_t gs = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t head = nullptr;
+    hipKernelNodeParams head_params{};
+    GroupArgs args{};            // argument of the replayed first kernel
+    void* arg_ptrs[1] = {nullptr};
+};
+
+namespace {
+
+void group_free(simlod_group* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->fork) (void)hipEventDestroy(g->fork);
+    if (g->join) (void)hipEventDestroy(g->join);
+    if (g->status_ev) (void)hipEventDestroy(g->status_ev);
+    if (g->gs) (void)hipStreamDestroy(g->gs);
+    if (g->d_table) (void)hipFree(g->d_table);
+    if (g->d_status) (void)hipFree(g->d_status);
+    if (g->h_status) (void)hipHostFree(g->h_status);
+    free_timing(g->tm);
+    free_timing(g->tune_tm);
+}
+
+// Marks members whose status word came back non-zero as poisoned.
+int group_poll(simlod_group* g, bool wait) {
+    if (!g->status_pending) return SIMLOD_OK;
+    const hipError_t e = wait ? hipEventSynchronize(g->status_ev) : hipEventQuery(g->status_ev);
+    if (e == hipErrorNotReady) return SIMLOD_OK;
+    g->status_pending = false;
+    if (e != hipSuccess) {
+        note_error("group status event", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    int rc = SIMLOD_OK;
+    for (size_t i = 0; i < g->members.size(); ++i) {
+        simlod_octree* h = g->members[i];
+        if (g->h_status[i] && !h->poisoned) {
+            h->poisoned = 1;
+            h->sticky = SIMLOD_ERR_CAPACITY;
+            rc = SIMLOD_ERR_CAPACITY;
+        }
+    }
+    return rc;
+}
+
+// Captures one pass (shape fixed, grid sizes from the members' capacity) on
+// the group's own stream and finds the first kernel's node.
+hipError_t group_capture(simlod_group* g, const GroupArgs& ga) {
+    const u32 cnt = (u32)g->members.size();
+    hipError_t e = hipStreamBeginCapture(g->gs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t pe = enqueue_group_pass(ga, g->cap_items, g->rounds, g->shape, nullptr, g->d_status,
+                                       g->gs);
+    if (pe == hipSuccess)
+        pe = hipMemcpyAsync(g->h_status, g->d_status, cnt * sizeof(u32), hipMemcpyDeviceToHost,
+                            g->gs);
+    e = hipStreamEndCapture(g->gs, &g->graph);
+    if (pe != hipSuccess) return pe;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return e;
+    size_t num = 0;
+    e = hipGraphGetNodes(g->graph, nullptr, &num);
+    if (e != hipSuccess) return e;
+    std::vector<hipGraphNode_t> nodes(num);
+    e = hipGraphGetNodes(g->graph, nodes.data(), &num);
+    if (e != hipSuccess) return e;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams p{};
+        if (hipGraphKernelNodeGetParams(nd, &p) != hipSuccess) continue;
+        if (p.func == count_leaves_kernel()) {
+            g->head = nd;
+            g->head_params = p;
+        }
+    }
+    return g->head ? hipSuccess : hipErrorInvalidValue;
+}
+
+// One pass: replayed from the graph when one is captured, else launched
+// (with the tuning shape and timing while tuning).
+hipError_t group_pass(simlod_group* g, const GroupArgs& ga, u64 items, hipStream_t s) {
+    const u32 cnt = (u32)g->members.size();
+    const bool tuning = (g->flags & SIMLOD_GROUP_AUTOTUNE) && !g->tuned;
+    if ((g->flags & SIMLOD_GROUP_GRAPH) && !tuning && !g->exec) {
+        const hipError_t ce = group_capture(g, ga);
+        if (ce != hipSuccess) {
+            note_error("group graph capture", ce);
+            return ce;
+        }
+    }
+    hipError_t e;
+    if (g->exec) {
+        g->args = ga;
+        g->arg_ptrs[0] = &g->args;
+        g->head_params.kernelParams = g->arg_ptrs;
+        g->head_params.extra = nullptr;
+        e = hipGraphExecKernelNodeSetParams(g->exec, g->head, &g->head_params);
+        if (e == hipSuccess) e = hipEventRecord(g->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(g->gs, g->fork, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(g->exec, g->gs);
+        if (e == hipSuccess) e = hipEventRecord(g->join, g->gs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, g->join, 0);
+    } else {
+        LaunchShape sh = g->shape;
+        Timing* tm = &g->tm;
+        u32 cand = 0;
+        if (tuning) {
+            cand = g->tune_pass % kTuneCands;
+            for (u32 k = 0; k < kNumShapes; ++k) sh.cap[k] = kTuneCaps[cand];
+            g->tune_tm.mask = 0;
+            for (u32 k = 0; k < kNumShapes; ++k) g->tune_tm.mask |= 1u << kShapeKernel[k];
+            std::memset(&g->tune_tm.acc, 0, sizeof(g->tune_tm.acc));
+            tm = &g->tune_tm;
+        }
+        e = enqueue_group_pass(ga, items, g->rounds, sh, tm, g->d_status, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->h_status, g->d_status, cnt * sizeof(u32), hipMemcpyDeviceToHost,
+                               s);
+        if (e == hipSuccess && tuning) {
+            drain_timing(g->tune_tm);  // waits for this pass
+            const double per = 1.0 / (double)std::max<u64>(items, 1);
+            for (u32 k = 0; k < kNumShapes; ++k)
+                g->tune_cost[k][cand] += g->tune_tm.acc.total_ms[kShapeKernel[k]] * per;
+            if (++g->tune_pass >= SIMLOD_TUNE_PASSES) {
+                for (u32 k = 0; k < kNumShapes; ++k) {
+                    u32 best = 0;
+                    for (u32 c = 1; c < kTuneCands; ++c)
+                        if (g->tune_cost[k][c] < g->tune_cost[k][best]) best = c;
+                    g->shape.cap[k] = kTuneCaps[best];
+                }
+                g->tuned = true;
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(g->status_ev, s);
+    if (e == hipSuccess) g->status_pending = true;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int simlod_group_create(simlod_octree* const* members, uint32_t count, uint32_t flags,
+                        simlod_group** out) {
+    if (!members || !out || count == 0 || count > SIMLOD_MAX_GROUP || count > kMaxMembers ||
+        (flags & ~(SIMLOD_GROUP_GRAPH | SIMLOD_GROUP_AUTOTUNE)))
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    u64 nodes = 0;
+    for (u32 i = 0; i < count; ++i) {
+        simlod_octree* h = members[i];
+        if (!h || h->poisoned || h->device != members[0]->device) return SIMLOD_ERR_INVALID_ARGUMENT;
+        for (u32 j = 0; j < i; ++j)
+            if (members[j] == h) return SIMLOD_ERR_INVALID_ARGUMENT;
+        nodes += h->cfg.max_nodes;
+    }
+    if (nodes >= (1ull << 32)) return SIMLOD_ERR_INVALID_ARGUMENT;  // member prefix sums are u32
+    DeviceGuard guard(members[0]->device);
+    clear_stale_error();
+    simlod_group* g = new (std::nothrow) simlod_group();
+    if (!g) return SIMLOD_ERR_OUT_OF_MEMORY;
+    g->members.assign(members, members + count);
+    g->device = members[0]->device;
+    g->flags = flags;
+    std::memset(&g->tm.acc, 0, sizeof(g->tm.acc));
+    std::memset(&g->tune_tm.acc, 0, sizeof(g->tune_tm.acc));
+    for (simlod_octree* h : g->members) {
+        g->rounds = std::max(g->rounds, expansion_rounds(h->cfg.max_depth));
+        g->cap_items += h->cfg.max_batch;
+    }
+    bool ok = hipMalloc((void**)&g->d_table, count * sizeof(Member)) == hipSuccess &&
+              hipMalloc((void**)&g->d_status, count * sizeof(u32)) == hipSuccess &&
+              hipHostMalloc((void**)&g->h_status, count * sizeof(u32), hipHostMallocDefault) ==
+                  hipSuccess &&
+              hipEventCreateWithFlags(&g->status_ev, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&g->join, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&g->gs, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        note_error("group allocation", hipGetLastError());
+        clear_stale_error();
+        group_free(g);
+        delete g;
+        return SIMLOD_ERR_OUT_OF_MEMORY;
+    }
+    std::memset(g->h_status, 0, count * sizeof(u32));
+    *out = g;
+    return SIMLOD_OK;
+}
+
+int simlod_group_insert(simlod_group* g, const simlod_point* const* pts, const uint64_t* n,
+                        void* stream) {
+    if (!g || !pts || !n) return SIMLOD_ERR_INVALID_ARGUMENT;
+    DeviceGuard guard(g->device);
+    const u32 cnt = (u32)g->members.size();
+    int rc = group_poll(g, false);
+    if (rc) return rc;
+    u64 passes = 0;
+    for (u32 i = 0; i < cnt; ++i) {
+        simlod_octree* h = g->members[i];
+        rc = poll_status(h, false);
+        if (rc) return rc;
+        if (n[i] == 0) continue;
+        if (!pts[i] || (reinterpret_cast<uintptr_t>(pts[i]) & 15u) || !is_device_ptr(pts[i]))
+            return SIMLOD_ERR_INVALID_ARGUMENT;
+        if (h->total_points + n[i] > 0xFFFFFFFFull) return SIMLOD_ERR_KEY_SPACE;
+        passes = std::max<u64>(passes, (n[i] + h->cfg.max_batch - 1) / h->cfg.max_batch);
+    }
+    clear_stale_error();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (u64 p = 0; p < passes; ++p) {
+        GroupArgs ga{};
+        ga.table = g->d_table;
+        ga.count = cnt;
+        u64 items = 0;
+        for (u32 i = 0; i < cnt; ++i) {
+            simlod_octree* h = g->members[i];
+            const u64 maxb = h->cfg.max_batch;
+            const u64 off = p * maxb;
+            const u64 m = off < n[i] ? std::min<u64>(maxb, n[i] - off) : 0u;
+            ga.m[i] = Member{h->d_tree,
+                             m ? reinterpret_cast<const uint4*>(pts[i] + off) : nullptr, (u32)m,
+                             (u32)(h->total_points + off)};
+            items += m;
+        }
+        const hipError_t e = group_pass(g, ga, items, s);
+        if (e != hipSuccess) {
+            note_error("group pass launch", e);
+            clear_stale_error();
+            for (simlod_octree* h : g->members) {
+                h->poisoned = 1;
+                h->sticky = SIMLOD_ERR_HIP;
+            }
+            return SIMLOD_ERR_HIP;
+        }
+    }
+    for (u32 i = 0; i < cnt; ++i) {
+        simlod_octree* h = g->members[i];
+        h->last_stream = s;
+        h->total_points += n[i];
+        h->passes += (n[i] + h->cfg.max_batch - 1) / h->cfg.max_batch;
+    }
+    g->last_stream = s;
+    return SIMLOD_OK;
+}
+
+int simlod_group_shape(simlod_group* g, uint32_t caps[4], uint32_t* state) {
+    if (!g || !caps) return SIMLOD_ERR_INVALID_ARGUMENT;
+    for (u32 k = 0; k < kNumShapes; ++k) caps[k] = g->shape.cap[k];
+    if (state) *state = (g->tuned ? 1u : 0u) | (g->exec ? 2u : 0u);
+    return SIMLOD_OK;
+}
+
+int simlod_group_set_kernel_timing(simlod_group* g, uint32_t kernel_mask) {
+    if (!g) return SIMLOD_ERR_INVALID_ARGUMENT;
+    DeviceGuard guard(g->device);
+    drain_timing(g->tm);
+    std::memset(&g->tm.acc, 0, sizeof(g->tm.acc));
+    g->tm.mask = kernel_mask & ((1u << SIMLOD_NUM_KERNELS) - 1u);
+    return SIMLOD_OK;
+}
+
+int simlod_group_get_kernel_times(simlod_group* g, simlod_kernel_times* out) {
+    if (!g || !out) return SIMLOD_ERR_INVALID_ARGUMENT;
+    DeviceGuard guard(g->device);
+    drain_timing(g->tm);
+    *out = g->tm.acc;
+    return SIMLOD_OK;
+}
+
+int simlod_group_sync(simlod_group* g) {
+    if (!g) return SIMLOD_ERR_INVALID_ARGUMENT;
+    DeviceGuard guard(g->device);
+    const hipError_t e = hipStreamSynchronize(g->last_stream);
+    if (e != hipSuccess) {
+        note_error("hipStreamSynchronize", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    return group_poll(g, true);
+}
+
+int simlod_group_destroy(simlod_group* g) {
+    if (!g) return SIMLOD_OK;
+    DeviceGuard guard(g->device);
+    hipError_t e = hipStreamSynchronize(g->last_stream);
+    if (g->gs) (void)hipStreamSynchronize(g->gs);
+    (void)hipGetLastError();
+    group_free(g);
+    delete g;
+    return e == hipSuccess ? SIMLOD_OK : SIMLOD_ERR_HIP;
+}
+
+int simlod_tune_chunk_capacity(const simlod_config* cfg, const simlod_point* sample, uint64_t n,
+                               const uint32_t* candidates, uint32_t count, void* stream,
+                               uint32_t* best, double* best_ms) {
+    if (!cfg || !candidates || count == 0 || !best || (n && !sample))
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double best_t = 0.0;
+    u32 best_c = 0;
+    for (u32 i = 0; i < count; ++i) {
+        simlod_config c = *cfg;
+        c.chunk_capacity = candidates[i];
+        simlod_octree* h = nullptr;
+        int rc = simlod_create(&c, &h);
+        if (rc) return rc;
+        DeviceGuard guard(h->device);
+        hipEvent_t a = nullptr, b = nullptr;
+        float ms = 0.f;
+        bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+                  hipEventRecord(a, s) == hipSuccess;
+        if (ok) rc = simlod_insert_batch(h, sample, n, stream);
+        ok = ok && rc == SIMLOD_OK && hipEventRecord(b, s) == hipSuccess &&
+             hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+        if (ok) rc = simlod_sync(h);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        (void)simlod_destroy(h);
+        if (rc) return rc;
+        if (!ok) {
+            note_error("chunk tuning", hipGetLastError());
+            clear_stale_error();
+            return SIMLOD_ERR_HIP;
+        }
+        if (i == 0 || ms < best_t) {
+            best_t = ms;
+            best_c = candidates[i];
+        }
+    }
+    *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return SIMLOD_OK;
+}
+
+// ------------------------------------------------------------------ serving
+}  // extern "C"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr u32 kServerInflight = 2;  // passes enqueued ahead of the device
+constexpr u32 kStatusRing = 4;      // pinned status arrays, > kServerInflight
+
+struct ServerRequest {
+    u64 ticket;
+    u32 slot;
+    const uint4* pts;
+    u32 n;
+    Clock::time_point t_submit;
+};
+
+struct ServerSlot {
+    simlod_octree* h = nullptr;
+    u64 bytes = 0;
+    bool open = false, opening = false, closing = false;
+    std::deque<ServerRequest> queue;
+    u64 queued_points = 0;
+    u32 inflight = 0;  // requests of this slot on the device
+};
+
+struct ServerPass {
+    hipEvent_t done = nullptr;
+    std::vector<ServerRequest> reqs;  // member i of the pass = reqs[i]
+    u32 ring = 0;
+};
+
+struct RequestResult {
+    int done = 0;
+    int status = SIMLOD_OK;
+    double latency_ms = 0.0;
+};
+
+}  // namespace
+
+struct simlod_server {
+    simlod_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_work;  // scheduler: requests queued or a pass retired
+    std::condition_variable cv_done;  // callers: requests completed
+    std::condition_variable cv_retire;  // completion thread: a pass was enqueued
+    std::vector<ServerSlot> slots;
+    std::deque<ServerPass*> inflight;
+    std::vector<hipEvent_t> free_events;
+    std::vector<RequestResult> results;  // by ticket - 1
+    u64 budget_used = 0;
+    u64 submitted = 0, completed = 0, passes = 0, points = 0;
+    u32 ring_next = 0;
+    hipStream_t stream = nullptr;
+    Member* d_table = nullptr;
+    u32* d_status = nullptr;  // kMaxMembers words
+    u32* h_status = nullptr;  // pinned, kStatusRing x kMaxMembers
+    bool stop = false;
+    std::thread scheduler, completer;
+};
+
+namespace {
+
+// Chooses the next pass's requests (lock held): the head request of every
+// open stream that has one (max_per_pass 0), else the max_per_pass oldest
+// heads.  Requests of poisoned streams complete at once with POISONED.
+std::vector<ServerRequest> server_pick(simlod_server* sv) {
+    std::vector<u32> heads;
+    for (u32 i = 0; i < sv->slots.size(); ++i) {
+        ServerSlot& sl = sv->slots[i];
+        while (!sl.queue.empty() && (sl.h == nullptr || sl.h->poisoned)) {
+            const ServerRequest& r = sl.queue.front();
+            sv->results[r.ticket - 1] = RequestResult{1, SIMLOD_ERR_POISONED, 0.0};
+            sl.queued_points -= r.n;
+            sl.queue.pop_front();
+            ++sv->completed;
+        }
+        if (!sl.queue.empty()) heads.push_back(i);
+    }
+    const u32 lim = sv->cfg.max_per_pass ? sv->cfg.max_per_pass : kMaxMembers;
+    if (heads.size() > lim) {
+        std::sort(heads.begin(), heads.end(), [&](u32 a, u32 b) {
+            return sv->slots[a].queue.front().ticket < sv->slots[b].queue.front().ticket;
+        });
+        heads.resize(lim);
+    }
+    std::vector<ServerRequest> out;
+    for (u32 i : heads) {
+        ServerSlot& sl = sv->slots[i];
+        out.push_back(sl.queue.front());
+        sl.queue.pop_front();
+        sl.queued_points -= out.back().n;
+        sl.inflight += 1;
+    }
+    return out;
+}
+
+void server_schedule(simlod_server* sv) {
+    (void)hipSetDevice(sv->cfg.device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_work.wait(lk, [&] {
+            if (sv->stop) return true;
+            if (sv->inflight.size() >= kServerInflight) return false;
+            for (const ServerSlot& sl : sv->slots)
+                if (!sl.queue.empty()) return true;
+            return false;
+        });
+        if (sv->stop) return;
+        std::vector<ServerRequest> reqs = server_pick(sv);
+        if (reqs.empty()) {
+            sv->cv_done.notify_all();
+            continue;
+        }
+        ServerPass* ps = new ServerPass();
+        ps->reqs = std::move(reqs);
+        ps->ring = sv->ring_next++ % kStatusRing;
+        if (!sv->free_events.empty()) {
+            ps->done = sv->free_events.back();
+            sv->free_events.pop_back();
+        } else {
+            (void)hipEventCreateWithFlags(&ps->done, hipEventDisableTiming);
+        }
+        GroupArgs ga{};
+        ga.table = sv->d_table;
+        ga.count = (u32)ps->reqs.size();
+        u64 items = 0;
+        u32 rounds = 1;
+        for (u32 i = 0; i < ga.count; ++i) {
+            const ServerRequest& r = ps->reqs[i];
+            simlod_octree* h = sv->slots[r.slot].h;
+            ga.m[i] = Member{h->d_tree, r.pts, r.n, (u32)h->total_points};
+            h->total_points += r.n;
+            h->passes += 1;
+            h->last_stream = sv->stream;
+            items += r.n;
+            rounds = std::max(rounds, expansion_rounds(h->cfg.max_depth));
+        }
+        u32* hs = sv->h_status + (u64)ps->ring * kMaxMembers;
+        std::memset(hs, 0, ga.count * sizeof(u32));
+        hipError_t e = enqueue_group_pass(ga, items, rounds, default_shape(), nullptr,
+                                          sv->d_status, sv->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs, sv->d_status, ga.count * sizeof(u32), hipMemcpyDeviceToHost,
+                               sv->stream);
+        if (e == hipSuccess) e = hipEventRecord(ps->done, sv->stream);
+        if (e != hipSuccess) {
+            note_error("server pass launch", e);
+            (void)hipGetLastError();
+            for (const ServerRequest& r : ps->reqs) {
+                sv->slots[r.slot].h->poisoned = 1;
+                sv->slots[r.slot].h->sticky = SIMLOD_ERR_HIP;
+            }
+            for (u32 i = 0; i < ga.count; ++i) hs[i] = 1u;
+            (void)hipEventRecord(ps->done, sv->stream);
+        }
+        sv->passes += 1;
+        sv->points += items;
+        sv->inflight.push_back(ps);
+        sv->cv_retire.notify_all();
+    }
+}
+
+void server_complete(simlod_server* sv) {
+    (void)hipSetDevice(sv->cfg.device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_retire.wait(lk, [&] { return sv->stop || !sv->inflight.empty(); });
+        if (sv->inflight.empty()) return;  // stopping, nothing on the device
+        ServerPass* ps = sv->inflight.front();
+        lk.unlock();
+        const hipError_t e = hipEventSynchronize(ps->done);
+        const Clock::time_point now = Clock::now();
+        lk.lock();
+        sv->inflight.pop_front();
+        const u32* hs = sv->h_status + (u64)ps->ring * kMaxMembers;
+        for (u32 i = 0; i < ps->reqs.size(); ++i) {
+            const ServerRequest& r = ps->reqs[i];
+            ServerSlot& sl = sv->slots[r.slot];
+            int st = SIMLOD_OK;
+            if (e != hipSuccess) {
+                st = SIMLOD_ERR_HIP;
+            } else if (hs[i]) {
+                st = SIMLOD_ERR_CAPACITY;
+            }
+            if (st && sl.h && !sl.h->poisoned) {
+                sl.h->poisoned = 1;
+                sl.h->sticky = st;
+            }
+            const double ms =
+                std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+            sv->results[r.ticket - 1] = RequestResult{1, st, ms};
+            sl.inflight -= 1;
+            ++sv->completed;
+        }
+        sv->free_events.push_back(ps->done);
+        delete ps;
+        sv->cv_work.notify_all();
+        sv->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int simlod_config_device_bytes(const simlod_config* cfg, uint64_t* bytes) {
+    if (!cfg || !bytes || !cfg_valid(cfg) || cfg->arena_bytes == 0)
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    simlod_octree dry;
+    u64 total = 0;
+    dry.dry = &total;
+    dry.cfg = *cfg;
+    (void)allocate_all(&dry, cfg, cfg->arena_bytes);
+    *bytes = total;
+    return SIMLOD_OK;
+}
+
+int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
+    if (!cfg || !out || cfg->max_streams == 0 || cfg->max_streams > SIMLOD_MAX_GROUP ||
+        cfg->max_streams > kMaxMembers || cfg->max_per_pass > kMaxMembers)
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+        clear_stale_error();
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
+    DeviceGuard guard(cfg->device);
+    clear_stale_error();
+    simlod_server* sv = new (std::nothrow) simlod_server();
+    if (!sv) return SIMLOD_ERR_OUT_OF_MEMORY;
+    sv->cfg = *cfg;
+    sv->slots.resize(cfg->max_streams);
+    bool ok = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc((void**)&sv->d_table, kMaxMembers * sizeof(Member)) == hipSuccess &&
+              hipMalloc((void**)&sv->d_status, kMaxMembers * sizeof(u32)) == hipSuccess &&
+              hipHostMalloc((void**)&sv->h_status, kStatusRing * kMaxMembers * sizeof(u32),
+                            hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        note_error("server allocation", hipGetLastError());
+        clear_stale_error();
+        if (sv->stream) (void)hipStreamDestroy(sv->stream);
+        if (sv->d_table) (void)hipFree(sv->d_table);
+        if (sv->d_status) (void)hipFree(sv->d_status);
+        if (sv->h_status) (void)hipHostFree(sv->h_status);
+        delete sv;
+        return SIMLOD_ERR_OUT_OF_MEMORY;
+    }
+    sv->scheduler = std::thread(server_schedule, sv);
+    sv->completer = std::thread(server_complete, sv);
+    *out = sv;
+    return SIMLOD_OK;
+}
+
+int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id) {
+    if (!sv || !cfg || !id || cfg->device != sv->cfg.device) return SIMLOD_ERR_INVALID_ARGUMENT;
+    u64 bytes = 0;
+    int rc = simlod_config_device_bytes(cfg, &bytes);
+    if (rc) return rc;
+    u32 slot = 0;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        while (slot < sv->slots.size() &&
+               (sv->slots[slot].open || sv->slots[slot].opening || sv->slots[slot].closing))
+            ++slot;
+        if (slot == sv->slots.size() || sv->budget_used + bytes > sv->cfg.hbm_budget)
+            return SIMLOD_ERR_BUSY;
+        sv->slots[slot].opening = true;
+        sv->budget_used += bytes;
+    }
+    simlod_octree* h = nullptr;
+    rc = simlod_create(cfg, &h);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    ServerSlot& sl = sv->slots[slot];
+    sl.opening = false;
+    if (rc) {
+        sv->budget_used -= bytes;
+        return rc;
+    }
+    sl.h = h;
+    sl.bytes = bytes;
+    sl.open = true;
+    sl.queued_points = 0;
+    sl.inflight = 0;
+    *id = slot;
+    return SIMLOD_OK;
+}
+
+int simlod_server_submit(simlod_server* sv, uint32_t id, const simlod_point* pts, uint64_t n,
+                         uint64_t* ticket) {
+    if (!sv || !ticket || (n && !pts)) return SIMLOD_ERR_INVALID_ARGUMENT;
+    if (n && ((reinterpret_cast<uintptr_t>(pts) & 15u) || !is_device_ptr(pts))) {
+        clear_stale_error();
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (id >= sv->slots.size() || !sv->slots[id].open || sv->slots[id].closing)
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    ServerSlot& sl = sv->slots[id];
+    if (sl.h->poisoned) return SIMLOD_ERR_POISONED;
+    if (n > sl.h->cfg.max_batch) return SIMLOD_ERR_INVALID_ARGUMENT;
+    if (sl.h->total_points + sl.queued_points + n > 0xFFFFFFFFull) return SIMLOD_ERR_KEY_SPACE;
+    const u64 t = sv->results.size() + 1;
+    sv->results.push_back(RequestResult{});
+    *ticket = t;
+    ++sv->submitted;
+    if (n == 0) {
+        sv->results[t - 1] = RequestResult{1, SIMLOD_OK, 0.0};
+        ++sv->completed;
+        return SIMLOD_OK;
+    }
+    sl.queue.push_back(ServerRequest{t, id, reinterpret_cast<const uint4*>(pts), (u32)n,
+                                     Clock::now()});
+    sl.queued_points += n;
+    sv->cv_work.notify_one();
+    return SIMLOD_OK;
+}
+
+int simlod_server_poll(simlod_server* sv, uint64_t ticket, int* done, double* latency_ms) {
+    if (!sv || !done) return SIMLOD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (ticket == 0 || ticket > sv->results.size()) return SIMLOD_ERR_INVALID_ARGUMENT;
+    const RequestResult& r = sv->results[ticket - 1];
+    *done = r.done;
+    if (latency_ms) *latency_ms = r.latency_ms;
+    return r.done ? r.status : SIMLOD_OK;
+}
+
+int simlod_server_drain(simlod_server* sv) {
+    if (!sv) return SIMLOD_ERR_INVALID_ARGUMENT;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_work.notify_all();
+    sv->cv_done.wait(lk, [&] { return sv->completed == sv->submitted; });
+    return SIMLOD_OK;
+}
+
+simlod_octree* simlod_server_octree(simlod_server* sv, uint32_t id) {
+    if (!sv) return nullptr;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    return id < sv->slots.size() && sv->slots[id].open ? sv->slots[id].h : nullptr;
+}
+
+int simlod_server_close(simlod_server* sv, uint32_t id) {
+    if (!sv) return SIMLOD_ERR_INVALID_ARGUMENT;
+    simlod_octree* h = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        if (id >= sv->slots.size() || !sv->slots[id].open || sv->slots[id].closing)
+            return SIMLOD_ERR_INVALID_ARGUMENT;
+        ServerSlot& sl = sv->slots[id];
+        sl.closing = true;
+        sv->cv_work.notify_all();
+        sv->cv_done.wait(lk, [&] { return sl.queue.empty() && sl.inflight == 0; });
+        h = sl.h;
+    }
+    const int rc = simlod_destroy(h);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    ServerSlot& sl = sv->slots[id];
+    sv->budget_used -= sl.bytes;
+    sl = ServerSlot{};
+    return rc;
+}
+
+int simlod_server_counters(simlod_server* sv, uint64_t out[4]) {
+    if (!sv || !out) return SIMLOD_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    out[0] = sv->passes;
+    out[1] = sv->completed;
+    out[2] = sv->points;
+    out[3] = sv->budget_used;
+    return SIMLOD_OK;
+}
+
+int simlod_server_destroy(simlod_server* sv) {
+    if (!sv) return SIMLOD_OK;
+    (void)simlod_server_drain(sv);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    sv->cv_retire.notify_all();
+    sv->scheduler.join();
+    sv->completer.join();
+    DeviceGuard guard(sv->cfg.device);
+    (void)hipStreamSynchronize(sv->stream);
+    int rc = SIMLOD_OK;
+    for (ServerSlot& sl : sv->slots)
+        if (sl.h && simlod_destroy(sl.h) != SIMLOD_OK) rc = SIMLOD_ERR_HIP;
+    for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(sv->stream);
+    (void)hipFree(sv->d_table);
+    (void)hipFree(sv->d_status);
+    (void)hipHostFree(sv->h_status);
+    delete sv;
+    return rc;
 }
 
 const char* simlod_last_error(void) { return g_last_error; }
@@ -718,6 +1557,7 @@ const char* simlod_status_string(int code) {
         case SIMLOD_ERR_POISONED: return "handle poisoned by an earlier error";
         case SIMLOD_ERR_KEY_SPACE: return "more than 2^32-1 points in one octree";
         case SIMLOD_ERR_NOT_FOUND: return "no node with that path";
+        case SIMLOD_ERR_BUSY: return "no stream slot or device-memory budget free";
         default: return "unknown status";
     }
 }

@@ -39,6 +39,8 @@
 #include "simlod.h"
 #include "launch.hpp"
 
+#include <algorithm>
+
 namespace simlod {
 
 constexpr u32 kWG = 256;
@@ -171,13 +173,14 @@ __device__ __forceinline__ void flush_count(const DevTree& t, u32 key, u32 c) {
 }
 
 // Called by the whole workgroup after each tile of a counting kernel: once
-// the LDS table holds kCountFlushAt entries, its counts go to global memory
-// and it starts empty, so inserts keep finding free entries within the
-// probe limit however many distinct keys the workgroup meets.
+// the LDS table holds kCountFlushAt entries, or when the next tile belongs
+// to another octree of the group (or there is none), its counts go to global
+// memory and it starts empty, so inserts keep finding free entries within
+// the probe limit however many distinct keys the workgroup meets.
 __device__ __forceinline__ void count_table_tile_end(const DevTree& t, u32* lkey, u32* lval,
-                                                     u32* fill) {
+                                                     u32* fill, bool force) {
     __syncthreads();
-    const bool flush = *fill >= kCountFlushAt;
+    const bool flush = force || *fill >= kCountFlushAt;
     __syncthreads();  // every thread has read `fill` before it changes
     if (!flush) return;
     for (u32 e = threadIdx.x; e < kLds; e += kWG) {
@@ -191,24 +194,94 @@ __device__ __forceinline__ void count_table_tile_end(const DevTree& t, u32* lkey
     __syncthreads();
 }
 
+// ------------------------------------------------------ group plumbing
+// Every kernel of a pass works on a group of octrees (a single insertion is a
+// group of one).  Its work space is the concatenation of the members' units
+// (tiles of kWG work items, or list entries); a unit never spans two members,
+// so the member, and with it the DevTree, is uniform over a workgroup's tile
+// or a wavefront's entry.
+
+// s_pre[c] = first unit of member c, s_pre[count] = total, from units(c) of
+// each member; returns the total.  Whole workgroup; count <= kMaxMembers.
+template <typename F>
+__device__ __forceinline__ u32 member_prefix(u32 count, u32* s_pre, F units) {
+    static_assert(kMaxMembers <= 2u * 64u && kMaxMembers <= kWG, "two wavefronts scan");
+    const u32 tid = threadIdx.x;
+    const u32 lane = lane_id();
+    u32 v = tid < count ? units(tid) : 0u;
+#pragma unroll
+    for (u32 o = 1; o < 64u; o <<= 1) {  // inclusive scan within the wavefront
+        const u32 y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    if (tid < kMaxMembers) s_pre[tid + 1u] = v;
+    __syncthreads();
+    if (tid >= 64u && tid < kMaxMembers) s_pre[tid + 1u] += s_pre[64];
+    if (tid == 0) s_pre[0] = 0u;
+    __syncthreads();
+    return s_pre[count];
+}
+
+// The member whose units contain x (s_pre non-decreasing, x < s_pre[count]),
+// made scalar: callers pass a workgroup- or wavefront-uniform x.
+__device__ __forceinline__ u32 member_of(const u32* s_pre, u32 count, u32 x) {
+    u32 lo = 0u, hi = count;  // s_pre[lo] <= x < s_pre[hi]
+    while (hi - lo > 1u) {
+        const u32 mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Tiles are visited in runs of kRunTiles consecutive tiles, dealt to the
+// workgroups in turn (XCD-aware): a workgroup meets its tiles in increasing
+// order, neighbouring tiles share nodes and cells, and dense bursts still
+// spread over all workgroups.  next_tile(tile) is the workgroup's next tile
+// after `tile`, or kNone.
+constexpr u32 kRunTiles = 4;
+
+__device__ __forceinline__ u32 first_tile() { return xcd_block() * kRunTiles; }
+
+__device__ __forceinline__ u32 next_tile(u32 tile, u32 ntiles) {
+    const u32 nx = (tile + 1u) % kRunTiles ? tile + 1u
+                                           : tile + 1u - kRunTiles + gridDim.x * kRunTiles;
+    return nx < ntiles ? nx : kNone;
+}
+
+// Reads a member of the group table into registers.
+__device__ __forceinline__ DevTree tree_of(const Member* M, u32 c) { return *M[c].tree; }
+
 // ---------------------------------------------------------- first round
 // Counts every batch point in its leaf.  All leaves are open in this round;
-// a leaf's total is its stored points plus this counter.
-__global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* batch, u32 n) {
+// a leaf's total is its stored points plus this counter.  Block 0 also
+// copies the members from the kernel argument into the device table the
+// pass's later kernels read.
+__global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
-    Counters* ctr = t.ctr;
-    if (wg_skip(ctr, nullptr)) return;
-    for (u32 i = threadIdx.x; i < kLds; i += kWG) {
+    __shared__ u32 s_pre[kMaxMembers + 1u];
+    const u32 tid = threadIdx.x;
+    const u32 count = ga.count;
+    const Member* M = ga.m;
+    if (blockIdx.x == 0 && tid < count) ga.table[tid] = M[tid];
+    for (u32 i = tid; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
     }
-    if (threadIdx.x == 0) lfill = 0u;
-    __syncthreads();
-    const u32 step = gridDim.x * kWG;
-    for (u32 base = xcd_block() * kWG; base < n; base += step) {
-        const u32 j = base + threadIdx.x;
+    if (tid == 0) lfill = 0u;
+    const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
+        return M[c].tree->ctr->status ? 0u : (M[c].n + kWG - 1u) / kWG;
+    });
+    for (u32 tile = first_tile(); tile < ntiles;) {
+        const u32 c = member_of(s_pre, count, tile);
+        const DevTree t = tree_of(M, c);
+        const uint4* batch = M[c].batch;
+        const u32 n = M[c].n;
+        const u32 j = (tile - s_pre[c]) * kWG + tid;
         u32 leaf = kNone;
         if (j < n) {
             u32 qx, qy, qz, depth;
@@ -223,11 +296,11 @@ __global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* ba
             else
                 count_leaf_global(t, leaf, r.len);
         }
-        count_table_tile_end(t, lkey, lval, &lfill);
+        const u32 nx = next_tile(tile, ntiles);
+        count_table_tile_end(t, lkey, lval, &lfill,
+                             nx == kNone || nx >= s_pre[c + 1u]);
+        tile = nx;
     }
-    __syncthreads();
-    for (u32 e = threadIdx.x; e < kLds; e += kWG)
-        if (lkey[e] != kNone) count_leaf_global(t, lkey[e], lval[e]);
 }
 
 // One workgroup per leaf counted in the first round.  A leaf whose stored
@@ -236,21 +309,26 @@ __global__ __launch_bounds__(256) void k_count_leaves(DevTree t, const uint4* ba
 // spill buffer (they are re-inserted with the batch) and its chunks pushed to
 // the pool (section "Chunks and the Chunk Pool").  Any other counted leaf is
 // final for the pass and listed with its number of new points.
-__global__ __launch_bounds__(256) void k_split_leaves(DevTree t) {
+__global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count) {
     __shared__ u32 s_dec[3];
     __shared__ i32 s_pool;
-    Counters* ctr = t.ctr;
-    if (wg_skip(ctr, nullptr)) return;
-    const u32 nt = min(ctr->touched_count, t.max_nodes);
+    __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
-    for (u32 it = blockIdx.x; it < nt; it += gridDim.x) {
-        const u32 L = t.touched[it];
+    const u32 total = member_prefix(count, s_pre, [&](u32 c) {
+        const DevTree* tp = M[c].tree;
+        return tp->ctr->status ? 0u : min(tp->ctr->touched_count, tp->max_nodes);
+    });
+    for (u32 it = blockIdx.x; it < total; it += gridDim.x) {
+        const u32 c = member_of(s_pre, count, it);
+        const DevTree t = tree_of(M, c);
+        Counters* ctr = t.ctr;
+        const u32 L = t.touched[it - s_pre[c]];
         if (tid == 0) {
-            const u32 c = t.cnt[L];
+            const u32 cn = t.cnt[L];
             const u32 stored = t.count[L];
             const u32 depth = t.geo[L].w;
             u32 pend = 0u, slot = 0u, sbase = 0u;
-            if ((u64)stored + c > (u64)t.T && depth < t.Dmax) {
+            if ((u64)stored + cn > (u64)t.T && depth < t.Dmax) {
                 slot = atomicAdd(&ctr->hist_top, 1u);
                 const u32 p = atomicAdd(&ctr->pending_count[1], 1u);
                 sbase = stored ? atomicAdd(&ctr->spill_count, stored) : 0u;
@@ -267,7 +345,7 @@ __global__ __launch_bounds__(256) void k_split_leaves(DevTree t) {
             } else {
                 const u32 p = atomicAdd(&ctr->final_count, 1u);
                 if (p < t.max_nodes)
-                    t.final_list[p] = make_uint2(L, c);
+                    t.final_list[p] = make_uint2(L, cn);
                 else
                     set_status(t, SIMLOD_OVF_WORK);
             }
@@ -320,33 +398,38 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // Round k >= 2: every point whose leaf is a pending root adds one to the
 // root's histogram at each of the kHistLevels levels below it (levels beyond
 // Dmax do not exist).  Round 2 walks all of W; later rounds only the items
-// counted in the round before.
-__global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batch, u32 n,
-                                                    u32 base_key, u32 round) {
+// counted in the round before.  Octrees without pending roots take no part.
+__global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
-    Counters* ctr = t.ctr;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->pending_count[round & 1u] = 0u;
-    if (wg_skip(ctr, &ctr->pending_count[(round - 1u) & 1u])) return;
-    for (u32 i = threadIdx.x; i < kLds; i += kWG) {
+    __shared__ u32 s_pre[kMaxMembers + 1u];
+    const u32 tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < count) M[tid].tree->ctr->pending_count[round & 1u] = 0u;
+    for (u32 i = tid; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
     }
-    if (threadIdx.x == 0) lfill = 0u;
-    __syncthreads();
-    const u32 S = ctr->spill_count;
-    const u32 nwork = S + n;
-    const uint8_t* prev = round >= 3u ? t.amask[(round - 1u) & 1u] : nullptr;
-    uint8_t* mark = t.amask[round & 1u];
-    const u32 step = gridDim.x * kWG;
-    for (u32 base = xcd_block() * kWG; base < nwork; base += step) {
-        const u32 j = base + threadIdx.x;
+    if (tid == 0) lfill = 0u;
+    const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
+        const Counters* ctr = M[c].tree->ctr;
+        return ctr->status || ctr->pending_count[(round - 1u) & 1u] == 0u
+                   ? 0u
+                   : (ctr->spill_count + M[c].n + kWG - 1u) / kWG;
+    });
+    for (u32 tile = first_tile(); tile < ntiles;) {
+        const u32 c = member_of(s_pre, count, tile);
+        const DevTree t = tree_of(M, c);
+        const u32 S = t.ctr->spill_count;
+        const u32 nwork = S + M[c].n;
+        const uint8_t* prev = round >= 3u ? ((round & 1u) ? t.amask[0] : t.amask[1]) : nullptr;
+        uint8_t* mark = (round & 1u) ? t.amask[1] : t.amask[0];
+        const u32 j = (tile - s_pre[c]) * kWG + tid;
         u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
         if (j < nwork && (!prev || prev[j])) {
             uint4 rec;
             u32 key;
-            fetch_work(t, batch, S, base_key, j, rec, key);
+            fetch_work(t, M[c].batch, S, M[c].base_key, j, rec, key);
             quantize3(t, rec, qx, qy, qz);
             const u32 leaf = find_leaf(t, qx, qy, qz, depth);
             slot = t.hslot[leaf];
@@ -367,11 +450,11 @@ __global__ __launch_bounds__(256) void k_count_hist(DevTree t, const uint4* batc
                     flush_count(t, key, r.len);
             }
         }
-        count_table_tile_end(t, lkey, lval, &lfill);
+        const u32 nx = next_tile(tile, ntiles);
+        count_table_tile_end(t, lkey, lval, &lfill,
+                             nx == kNone || nx >= s_pre[c + 1u]);
+        tile = nx;
     }
-    __syncthreads();
-    for (u32 e = threadIdx.x; e < kLds; e += kWG)
-        if (lkey[e] != kNone) flush_count(t, lkey[e], lval[e]);
 }
 
 // Exclusive prefix sum of a[0..n) in LDS by one workgroup; returns the total.
@@ -430,23 +513,29 @@ __device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
 // descendants receive 8 consecutive children each (one node-count atomic per
 // root, in level order), occupancy grids (cleared later, in k_alloc) and
 // directory entries.
-__global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
+__global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 round) {
     __shared__ u32 s_h[kHistEntries];   // the root's histogram
     __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
     __shared__ u32 s_sp[kSplitSlots];   // split index of inner nodes
     __shared__ u32 s_q[kTreeSlots];     // scan buffer
     __shared__ u32 s_part[kWG + 1u];
     __shared__ u32 s_alloc[8];
-    Counters* ctr = t.ctr;
-    const u32* in_count = &ctr->pending_count[(round - 1u) & 1u];
-    if (wg_skip(ctr, in_count)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr->build_rounds, 1u);
-    const u32 nroots = min(*in_count, t.max_nodes);
-    const u32* roots = t.pending[(round - 1u) & 1u];
-    const u32 out = round & 1u;
+    __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
-    for (u32 it = blockIdx.x; it < nroots; it += gridDim.x) {
-        const u32 X = roots[it];
+    const u32 total = member_prefix(count, s_pre, [&](u32 c) {
+        const DevTree* tp = M[c].tree;
+        const Counters* ctr = tp->ctr;
+        return ctr->status ? 0u : min(ctr->pending_count[(round - 1u) & 1u], tp->max_nodes);
+    });
+    if (blockIdx.x == 0 && tid < count && s_pre[tid + 1u] > s_pre[tid])
+        atomicAdd(&M[tid].tree->ctr->build_rounds, 1u);
+    const u32 out = round & 1u;
+    for (u32 it = blockIdx.x; it < total; it += gridDim.x) {
+        const u32 c = member_of(s_pre, count, it);
+        const DevTree t = tree_of(M, c);
+        Counters* ctr = t.ctr;
+        u32* const pend_out = out ? t.pending[1] : t.pending[0];  // select: no indexed copy
+        const u32 X = (out ? t.pending[0] : t.pending[1])[it - s_pre[c]];
         const uint4 gx = t.geo[X];
         const u32 d0 = gx.w;
         const u32* hsrc = t.hist + (u64)t.hslot[X] * kHistEntries;
@@ -507,7 +596,7 @@ __global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
             s_alloc[5] = pb;
         }
         __syncthreads();
-        if (!s_alloc[0]) break;  // poisoned: later kernels do nothing
+        if (!s_alloc[0]) continue;  // octree poisoned: later kernels skip it
         const u32 base = s_alloc[1], gbase = s_alloc[2], zbase = s_alloc[3];
         const u32 hb = s_alloc[4], pb = s_alloc[5];
         const u32 xidx = d0 <= t.dir_depth ? dir_index(t.K, d0, gx.x, gx.y, gx.z) : 0u;
@@ -539,7 +628,7 @@ __global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
             }
             if (f & kFPending) {
                 t.hslot[nd] = hb + s_q[i];
-                t.pending[out][pb + s_q[i]] = nd;
+                pend_out[pb + s_q[i]] = nd;
             } else {
                 t.hslot[nd] = kNone;
             }
@@ -570,7 +659,7 @@ __global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
             s_alloc[6] = fb;
         }
         __syncthreads();
-        if (!s_alloc[0]) break;
+        if (!s_alloc[0]) continue;
         const u32 fb = s_alloc[6];
         for (u32 i = 1u + tid; i < kTreeSlots; i += kWG) {
             if (!(s_f[i] & kFFinal)) continue;
@@ -591,25 +680,46 @@ __global__ __launch_bounds__(256) void k_build(DevTree t, u32 round) {
 // and linked after its last chunk.
 // The first call of a pass (points) also clears the occupancy grids of the
 // pass's new inner nodes, spread over the whole grid.
-__global__ __launch_bounds__(256) void k_alloc(DevTree t, u32 voxels) {
-    Counters* ctr = t.ctr;
-    if (__builtin_amdgcn_readfirstlane(ctr->status)) return;  // wave-uniform
+constexpr u32 kZeroPiece = 4096;  // uint4 stores per workgroup visit of a new grid
+
+__global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 voxels) {
+    __shared__ u32 s_zpre[kMaxMembers + 1u];
+    __shared__ u32 s_pre[kMaxMembers + 1u];
     if (!voxels) {
-        const u32 nz = min(ctr->zero_count, t.max_nodes);
-        const u32 per = t.grid_blocks * (kBlockBytes / 16u);
-        const u64 total = (u64)nz * per;
-        for (u64 i = (u64)blockIdx.x * kWG + threadIdx.x; i < total; i += (u64)gridDim.x * kWG) {
-            const u32 z = (u32)(i / per);
-            reinterpret_cast<uint4*>(block_ptr(t, t.zero_list[z]))[i - (u64)z * per] =
-                make_uint4(0u, 0u, 0u, 0u);
+        // pieces of kZeroPiece uint4 of each new grid, one workgroup each
+        const u32 ztotal = member_prefix(count, s_zpre, [&](u32 c) {
+            const DevTree* tp = M[c].tree;
+            const u32 per = tp->grid_blocks * (kBlockBytes / 16u);
+            return tp->ctr->status ? 0u
+                                   : min(tp->ctr->zero_count, tp->max_nodes) *
+                                         ((per + kZeroPiece - 1u) / kZeroPiece);
+        });
+        for (u32 zi = blockIdx.x; zi < ztotal; zi += gridDim.x) {
+            const u32 c = member_of(s_zpre, count, zi);
+            const DevTree t = tree_of(M, c);
+            const u32 per = t.grid_blocks * (kBlockBytes / 16u);
+            const u32 pieces = (per + kZeroPiece - 1u) / kZeroPiece;
+            const u32 z = (zi - s_zpre[c]) / pieces;
+            const u32 lo = ((zi - s_zpre[c]) - z * pieces) * kZeroPiece;
+            const u32 hi = min(lo + kZeroPiece, per);
+            uint4* g = reinterpret_cast<uint4*>(block_ptr(t, t.zero_list[z]));
+            for (u32 i = lo + threadIdx.x; i < hi; i += kWG) g[i] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
-    u32 n = voxels ? ctr->vtouched_count : ctr->final_count;
-    n = min(n, t.max_nodes);
+    const u32 ntotal = member_prefix(count, s_pre, [&](u32 c) {
+        const DevTree* tp = M[c].tree;
+        const Counters* ctr = tp->ctr;
+        return ctr->status ? 0u
+                           : min(voxels ? ctr->vtouched_count : ctr->final_count, tp->max_nodes);
+    });
     const u32 lane = lane_id();
     const u32 wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
     const u32 nwaves = gridDim.x * (kWG >> 6);
-    for (u32 e = wave; e < n; e += nwaves) {
+    for (u32 ew = wave; ew < ntotal; ew += nwaves) {
+        const u32 c = member_of(s_pre, count, ew);
+        const DevTree t = tree_of(M, c);
+        Counters* ctr = t.ctr;
+        const u32 e = ew - s_pre[c];
         u32 node, added;
         if (voxels) {
             node = t.vtouched[e];
@@ -738,16 +848,34 @@ __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 nod
     }
 }
 
-// Candidate table of one tile: (node << 24 | cell) -> min (key << 32 | rgba).
-__device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 val) {
+// Candidate table of a workgroup.  A live entry maps (node << 24 | cell) to
+// the minimum (key << 32 | rgba) of the current tile; an entry flagged
+// kSubmitted remembers a cell the workgroup already claimed in an earlier
+// tile, with a smaller key than any batch item it meets later (its tiles run
+// in increasing work index, batch keys increase with the index, and spilled
+// items carry keys below every batch key).  A batch item on such a cell is
+// dominated: its claim could not lower the cell's minimum, so it is dropped
+// without touching global memory.  Submitted entries are only a cache: any
+// may be overwritten by a new live entry.  Returns false when no entry was
+// found within the probe limit.
+constexpr u64 kSubmitted = 1ull << 63;  // tags use bits 0..55
+
+__device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 val,
+                                            bool batch_item) {
     u32 h = (u32)(mix64(tag) >> (64u - kCandBits));
     for (u32 p = 0; p < 64u; ++p) {
-        const u64 cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)kEmptyTag,
-                                  (unsigned long long)tag);
-        if (cur == kEmptyTag || cur == tag) {
+        u64 cur = ctag[h];
+        if (cur != tag && (cur == kEmptyTag || (cur & kSubmitted)) &&
+            !(batch_item && cur == (tag | kSubmitted)))
+            cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)cur,
+                            (unsigned long long)tag) == cur
+                      ? tag
+                      : ctag[h];
+        if (cur == tag) {
             atomicMin((unsigned long long*)&cval[h], (unsigned long long)val);
             return true;
         }
+        if (batch_item && cur == (tag | kSubmitted)) return true;
         h = (h + 1u) & (kCands - 1u);
     }
     return false;
@@ -761,9 +889,10 @@ __device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 v
 // after the traversal.  Must be reached by the whole wave.
 __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
-                                                 u32 rgba, u32 lane, u64* ctag, u64* cval,
-                                                 u32 stripe, u32* s_claims, u32* s_nclaims,
-                                                 u32* s_vkey, u32* s_vcnt, u32* s_vfill) {
+                                                 u32 rgba, bool batch_item, u32 lane, u64* ctag,
+                                                 u64* cval, u32 stripe, u32* s_claims,
+                                                 u32* s_nclaims, u32* s_vkey, u32* s_vcnt,
+                                                 u32* s_vfill) {
     u64 tag = kEmptyTag;
     if (inner) {
         const u32 lin = cell_lin(qx, qy, qz, t.Dmax - d, t.r, t.R - 1u);
@@ -774,7 +903,7 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
-    if (cand && !cand_insert(ctag, cval, tag, val)) {  // table full: claim right away
+    if (cand && !cand_insert(ctag, cval, tag, val, batch_item)) {  // no entry: claim now
         u32 hslot;
         if (claim_cell(t, tag, val, hslot))
             stage_claim(t, hslot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt, s_vfill);
@@ -791,14 +920,21 @@ struct ClaimBatch {
     u32 hh[kCandPer];
 };
 
-__device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval, ClaimBatch& b) {
+// keep: the workgroup's next tile belongs to the same octree, so submitted
+// cells stay in the table as dominance markers; otherwise it starts empty.
+__device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval, ClaimBatch& b,
+                                            bool keep) {
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k) {
         const u32 i = threadIdx.x + k * 256u;
-        b.tg[k] = ctag[i];
+        const u64 tg = ctag[i];
+        const bool live = tg != kEmptyTag && !(tg & kSubmitted);
+        b.tg[k] = live ? tg : kEmptyTag;
         b.vl[k] = cval[i];
-        ctag[i] = kEmptyTag;
-        cval[i] = ~0ull;
+        if (live || !keep) {
+            ctag[i] = live && keep ? (tg | kSubmitted) : kEmptyTag;
+            cval[i] = ~0ull;
+        }
         b.hh[k] = (u32)mix64(b.tg[k]) & t.hmask;
     }
 #pragma unroll
@@ -885,15 +1021,13 @@ __device__ void flush_staged(const DevTree& t, u32 stripe, u32* s_claims, u32* s
 // voxel counts are summed in LDS and flushed once per workgroup, and claimed
 // cells are staged in LDS and appended with one atomic per workgroup on one
 // of kStripes counters (workgroup id mod kStripes, i.e. one per XCD).
-__global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* batch, u32 n,
-                                                      u32 base_key) {
+__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count) {
     __shared__ u32 s_claims[kClaimBuf];
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
     __shared__ u64 s_ctag[kCands], s_cval[kCands];
     __shared__ u32 s_nclaims, s_flush, s_vfill;
-    Counters* ctr = t.ctr;
-    if (wg_skip(ctr, nullptr)) return;
+    __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     for (u32 i = tid; i < kCands; i += kWG) {
         s_ctag[i] = kEmptyTag;
@@ -911,20 +1045,31 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         s_nclaims = 0u;
         s_vfill = 0u;
     }
-    __syncthreads();
-
-    const u32 S = ctr->spill_count;
-    const u32 nwork = S + n;
+    const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
+        const Counters* ctr = M[c].tree->ctr;
+        return ctr->status ? 0u : (ctr->spill_count + M[c].n + kWG - 1u) / kWG;
+    });
     const u32 lane = lane_id();
-    const u32 rmask = t.R - 1u;
     const u32 stripe = blockIdx.x % kStripes;
-    const u32 step = gridDim.x * kWG;
-    u32 base = xcd_block() * kWG;
+    // work item j of member c's tile: its record and key
+    auto fetch = [&](u32 c, u32 tile, uint4& rec, u32& key) {
+        const DevTree* tp = M[c].tree;
+        const u32 S = tp->ctr->spill_count;
+        const u32 j = (tile - s_pre[c]) * kWG + tid;
+        if (j < S + M[c].n) fetch_work(*tp, M[c].batch, S, M[c].base_key, j, rec, key);
+    };
+    u32 tile = first_tile();
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
     u32 key_n = 0u;
-    if (base + tid < nwork) fetch_work(t, batch, S, base_key, base + tid, rec_n, key_n);
-    for (; base < nwork; base += step) {
-        const bool valid = base + tid < nwork;
+    if (tile < ntiles) fetch(member_of(s_pre, count, tile), tile, rec_n, key_n);
+    while (tile < ntiles) {
+        const u32 c = member_of(s_pre, count, tile);
+        const DevTree t = tree_of(M, c);
+        const u32 S = t.ctr->spill_count;
+        const u32 j = (tile - s_pre[c]) * kWG + tid;
+        const bool valid = j < S + M[c].n;
+        const bool batch_item = j >= S;
+        const u32 rmask = t.R - 1u;
         const uint4 rec = rec_n;
         const u32 key = key_n;
         u32 qx = 0u, qy = 0u, qz = 0u;
@@ -960,16 +1105,16 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
                 leaf = ed == kNone ? 0u : ed;
                 desc = false;
             }
-            level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w, lane,
-                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt,
-                             &s_vfill);
+            level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w,
+                             batch_item, lane, s_ctag, s_cval, stripe, s_claims, &s_nclaims,
+                             s_vkey, s_vcnt, &s_vfill);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
         if (desc) node = t.child[e[D] & ~kDirInner] + octant_of(qx, qy, qz, t.K - 1u - D);
         for (u32 d = D + 1u; d <= t.Dmax; ++d) {
-            const u32 c = desc && d < t.Dmax ? t.child[node] : 0u;
-            const bool inner = desc && c != 0u;
+            const u32 ch = desc && d < t.Dmax ? t.child[node] : 0u;
+            const bool inner = desc && ch != 0u;
             if (desc && !inner) {
                 leaf = node;
                 desc = false;
@@ -977,9 +1122,10 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             if (__ballot(inner) == 0ull) break;
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
-            level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, lane, s_ctag,
-                             s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
-            if (inner) node = c + octant_of(qx, qy, qz, t.K - 1u - d);
+            level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, batch_item, lane,
+                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt,
+                             &s_vfill);
+            if (inner) node = ch + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
         // leaf slots: LDS histogram of the tile
@@ -992,19 +1138,20 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
         }
         le = __shfl(le, r.head);
         r0 = __shfl(r0, r.head) + r.rank;
+        const u32 nx = next_tile(tile, ntiles);
+        const u32 cn = nx == kNone ? kNone : member_of(s_pre, count, nx);
         __syncthreads();
         // one round trip for the tile: claim CASes, one slot reservation per
         // leaf, and the next tile's records
         ClaimBatch cb;
-        claim_issue(t, s_ctag, s_cval, cb);
+        claim_issue(t, s_ctag, s_cval, cb, cn == c);
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
             s_lkey[i] = kNone;
             s_lcnt[i] = 0u;
         }
-        if (base + step + tid < nwork)
-            fetch_work(t, batch, S, base_key, base + step + tid, rec_n, key_n);
+        if (nx != kNone) fetch(cn, nx, rec_n, key_n);
         claim_resolve(t, cb, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         __syncthreads();
         if (valid) {
@@ -1020,13 +1167,15 @@ __global__ __launch_bounds__(256) void k_sample_store(DevTree t, const uint4* ba
             }
         }
         // Staged claims and node counts go out before the buffers can
-        // overflow in the next tile.  The decision is read by every thread
-        // before the barrier and changed by none until after it: uniform.
-        const bool flush = s_nclaims > kClaimFlushAt || s_vfill >= kNodeFlushAt;
+        // overflow in the next tile, and before the workgroup moves on to
+        // another octree (or has no tile left).  The decision is read by
+        // every thread before the barrier and changed by none until after
+        // it: uniform.
+        const bool flush = cn != c || s_nclaims > kClaimFlushAt || s_vfill >= kNodeFlushAt;
         __syncthreads();
         if (flush) flush_staged(t, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill, &s_flush);
+        tile = nx;
     }
-    flush_staged(t, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill, &s_flush);
 }
 
 // ------------------------------------------------------- voxel stores
@@ -1037,12 +1186,11 @@ constexpr u32 kWordBits = 9;  // grid words touched per tile, merged in LDS
 // set, and the claim-table entry is cleared for the next pass.  Slots are
 // reserved per (workgroup, node) after an LDS histogram of the tile, and the
 // tile's bits are OR-ed per grid word in LDS before one atomic per word.
-__global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
+__global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count) {
     __shared__ u32 s_nkey[1u << kSlotBits], s_ncnt[1u << kSlotBits], s_nbase[1u << kSlotBits];
     __shared__ u64 s_wkey[1u << kWordBits];
     __shared__ u32 s_wbits[1u << kWordBits];
-    Counters* ctr = t.ctr;
-    if (wg_skip(ctr, nullptr)) return;
+    __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
         s_nkey[i] = kNone;
@@ -1052,14 +1200,26 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
         s_wkey[i] = kEmptyTag;
         s_wbits[i] = 0u;
     }
-    __syncthreads();
-    u32 pre[kStripes + 1];
-    pre[0] = 0u;
-    for (u32 s = 0; s < kStripes; ++s) pre[s + 1] = pre[s] + min(ctr->claim_count[s], t.claim_cap);
-    const u32 n = pre[kStripes];
-    const u32 rmask = t.R - 1u;
-    const u32 step = gridDim.x * kWG;
-    for (u32 base = blockIdx.x * kWG; base < n; base += step) {
+    // tiles of each octree's claims (all stripes, in stripe order)
+    const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
+        const DevTree* tp = M[c].tree;
+        const Counters* ctr = tp->ctr;
+        if (ctr->status) return 0u;
+        u32 n = 0u;
+        for (u32 s = 0; s < kStripes; ++s) n += min(ctr->claim_count[s], tp->claim_cap);
+        return (n + kWG - 1u) / kWG;
+    });
+    for (u32 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const u32 c = member_of(s_pre, count, tile);
+        const DevTree t = tree_of(M, c);
+        Counters* ctr = t.ctr;
+        u32 pre[kStripes + 1];
+        pre[0] = 0u;
+        for (u32 s = 0; s < kStripes; ++s)
+            pre[s + 1] = pre[s] + min(ctr->claim_count[s], t.claim_cap);
+        const u32 n = pre[kStripes];
+        const u32 rmask = t.R - 1u;
+        const u32 base = (tile - s_pre[c]) * kWG;
         const u32 i = base + tid;
         const bool valid = i < n;
         u32 h = 0u, node = kNone, lin = 0u;
@@ -1146,10 +1306,15 @@ __global__ __launch_bounds__(256) void k_store_voxels(DevTree t) {
 }
 
 // ------------------------------------------------------- bookkeeping
-__global__ void k_finish(DevTree t) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One thread per member: per-pass counters cleared, statistics added.
+// status_out (may be null) receives each member's status word.
+__global__ void k_finish(const Member* M, u32 count, u32* status_out) {
+    const u32 m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    const DevTree& t = *M[m].tree;
     Counters* c = t.ctr;
-    if (c->status) return;
+    if (status_out) status_out[m] = c->status;
+    if (c->status || M[m].n == 0u) return;  // an empty share did no work
     if (c->pool_top < 0) c->pool_top = 0;
     u32 claims = 0u;
     for (u32 k = 0; k < kStripes; ++k) claims += min(c->claim_count[k], t.claim_cap);
@@ -1233,41 +1398,53 @@ static inline u32 grid_for(u64 items, u32 lo, u32 hi) {
 
 u32 expansion_rounds(u32 max_depth) { return 1u + (max_depth + kHistLevels - 1u) / kHistLevels; }
 
-hipError_t launch_count_leaves(const DevTree& t, const uint4* batch, u32 n, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_leaves, dim3(grid_for(n, 8, 1024)), dim3(kWG), 0, s, t, batch, n);
-    return hipGetLastError();
-}
-hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s) {
-    hipLaunchKernelGGL(k_split_leaves, dim3(grid_for((u64)n / 64u, 64, 1024)), dim3(kWG), 0, s, t);
-    return hipGetLastError();
-}
-hipError_t launch_count_hist(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
-                             hipStream_t s) {
-    const u32 g = round == 2u ? grid_for((u64)n + 65536u, 64, 1024) : grid_for((u64)n / 4u, 32, 512);
-    hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key, round);
-    return hipGetLastError();
-}
-hipError_t launch_build(const DevTree& t, u32 round, hipStream_t s) {
-    hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, t, round);
-    return hipGetLastError();
-}
-hipError_t launch_alloc(const DevTree& t, u32 voxels, hipStream_t s) {
-    hipLaunchKernelGGL(k_alloc, dim3(voxels ? 256 : 1024), dim3(kWG), 0, s, t, voxels);
-    return hipGetLastError();
-}
-hipError_t launch_sample_store(const DevTree& t, const uint4* batch, u32 n, u32 base_key,
+const void* count_leaves_kernel() { return reinterpret_cast<const void*>(&k_count_leaves); }
+
+// Grid sizes depend only on `items`, the pass's batch points summed over the
+// group (or a capacity for a pass captured in a graph), and the launch shape,
+// never on device-side counts: every kernel loops over whatever work it finds.
+
+hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s) {
-    u32 g = grid_for((u64)n + 4096u, 64, 1024);
-    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, t, batch, n, base_key);
+    const u32 g = grid_for(items, 8, sh.cap[kShapeCount]);
+    hipLaunchKernelGGL(k_count_leaves, dim3(g), dim3(kWG), 0, s, ga);
     return hipGetLastError();
 }
-hipError_t launch_store_voxels(const DevTree& t, u32 n, hipStream_t s) {
-    u32 g = grid_for(n, 64, 1024);
-    hipLaunchKernelGGL(k_store_voxels, dim3(g), dim3(kWG), 0, s, t);
+hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s) {
+    hipLaunchKernelGGL(k_split_leaves, dim3(grid_for(items / 64u, 64, 1024)), dim3(kWG), 0, s, m,
+                       count);
     return hipGetLastError();
 }
-hipError_t launch_finish(const DevTree& t, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, t);
+hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
+                             const LaunchShape& sh, hipStream_t s) {
+    const u32 cap = sh.cap[kShapeHist];
+    const u32 g = round == 2u ? grid_for(items + 65536u, 64, cap)
+                              : grid_for(items / 4u, 32, std::max<u32>(cap / 2u, 32u));
+    hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, m, count, round);
+    return hipGetLastError();
+}
+hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
+    hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, m, count, round);
+    return hipGetLastError();
+}
+hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
+    hipLaunchKernelGGL(k_alloc, dim3(voxels ? 256 : 1024), dim3(kWG), 0, s, m, count, voxels);
+    return hipGetLastError();
+}
+hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                               hipStream_t s) {
+    const u32 g = grid_for(items + 4096u, 64, sh.cap[kShapeSample]);
+    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count);
+    return hipGetLastError();
+}
+hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                               hipStream_t s) {
+    const u32 g = grid_for(items, 64, sh.cap[kShapeStore]);
+    hipLaunchKernelGGL(k_store_voxels, dim3(g), dim3(kWG), 0, s, m, count);
+    return hipGetLastError();
+}
+hipError_t launch_finish(const Member* m, u32 count, u32* status_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kMaxMembers), 0, s, m, count, status_out);
     return hipGetLastError();
 }
 hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {

@@ -9,17 +9,28 @@
 
 namespace simlod {
 
+// Largest workgroup count of each per-point kernel (the launch shape a group
+// autotunes); each launch uses min(cap, what its items need).
+enum ShapeKind : u32 { kShapeCount = 0, kShapeHist, kShapeSample, kShapeStore, kNumShapes };
+struct LaunchShape {
+    u32 cap[kNumShapes];
+};
+inline LaunchShape default_shape() { return LaunchShape{{1024u, 1024u, 1024u, 1024u}}; }
+
 u32 expansion_rounds(u32 max_depth);
-hipError_t launch_count_leaves(const DevTree& t, const uint4* batch, u32 n, hipStream_t s);
-hipError_t launch_split_leaves(const DevTree& t, u32 n, hipStream_t s);
-hipError_t launch_count_hist(const DevTree& t, const uint4* batch, u32 n, u32 base_key, u32 round,
-                             hipStream_t s);
-hipError_t launch_build(const DevTree& t, u32 round, hipStream_t s);
-hipError_t launch_alloc(const DevTree& t, u32 voxels, hipStream_t s);
-hipError_t launch_sample_store(const DevTree& t, const uint4* batch, u32 n, u32 base_key,
+const void* count_leaves_kernel();  // the pass's first kernel (graph replay)
+hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s);
-hipError_t launch_store_voxels(const DevTree& t, u32 n, hipStream_t s);
-hipError_t launch_finish(const DevTree& t, hipStream_t s);
+hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s);
+hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
+                             const LaunchShape& sh, hipStream_t s);
+hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s);
+hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s);
+hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                               hipStream_t s);
+hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                               hipStream_t s);
+hipError_t launch_finish(const Member* m, u32 count, u32* status_out, hipStream_t s);
 hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s);
 hipError_t launch_gather(const DevTree& t, const u32* nodes, const u64* first, u32 nn,
                          uint4* out_rec, u32* out_key, hipStream_t s);

@@ -131,6 +131,28 @@ struct DevTree {
     u32 chunk_blocks, grid_blocks, grid_words;
 };
 
+// One octree's share of an insertion pass over a group of octrees: its
+// device-resident DevTree, its batch (device memory, 16-byte records) and the
+// key of the batch's first point.  A single-octree pass is a group of one.
+struct Member {
+    const DevTree* tree;
+    const uint4* batch;
+    u32 n;
+    u32 base_key;
+};
+
+constexpr u32 kMaxMembers = 128;  // octrees per group pass (<= two wavefronts)
+
+// Argument of a pass's first kernel: the members inline (so that a replayed
+// graph only needs this one node's arguments changed) and the device table
+// it copies them to for the pass's later kernels.
+struct GroupArgs {
+    Member* table;
+    u32 count;
+    u32 pad;
+    Member m[kMaxMembers];
+};
+
 __device__ __forceinline__ uint8_t* block_ptr(const DevTree& t, u32 blk) {
     return t.arena + (u64)blk * kBlockBytes;
 }

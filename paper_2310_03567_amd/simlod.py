@@ -26,6 +26,12 @@ ERR_CAPACITY = -4
 ERR_POISONED = -5
 ERR_KEY_SPACE = -6
 ERR_NOT_FOUND = -7
+ERR_BUSY = -8
+
+GROUP_GRAPH = 0x1
+GROUP_AUTOTUNE = 0x2
+MAX_GROUP = 128
+TUNE_PASSES = 10
 
 OVF_NODES, OVF_ARENA, OVF_SPILL, OVF_BACKLOG, OVF_WORK, OVF_HASH = 1, 2, 4, 8, 16, 32
 OVF_INTERNAL, OVF_HIST = 64, 128
@@ -79,6 +85,12 @@ class StatsData(ctypes.Structure):
         "max_new_voxels", "sum_rounds", "sum_spilled", "sum_new_voxels")] + [("status_bits", ctypes.c_uint32), ("poisoned", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("max_streams", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("max_per_pass", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class KernelTimes(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64 * 9), ("total_ms", ctypes.c_double * 9)]
 
@@ -97,6 +109,36 @@ EXPORTS = {
     "simlod_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_set_kernel_timing": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
     "simlod_get_kernel_times": ([ctypes.c_void_p, ctypes.POINTER(KernelTimes)], ctypes.c_int),
+    "simlod_group_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint32,
+                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "simlod_group_insert": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p], ctypes.c_int),
+    "simlod_group_shape": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "simlod_group_set_kernel_timing": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
+    "simlod_group_get_kernel_times": ([ctypes.c_void_p, ctypes.POINTER(KernelTimes)],
+                                      ctypes.c_int),
+    "simlod_group_sync": ([ctypes.c_void_p], ctypes.c_int),
+    "simlod_group_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "simlod_tune_chunk_capacity": ([ctypes.POINTER(Config), ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "simlod_config_device_bytes": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_uint64)],
+                                   ctypes.c_int),
+    "simlod_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)],
+                             ctypes.c_int),
+    "simlod_server_open": ([ctypes.c_void_p, ctypes.POINTER(Config),
+                           ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "simlod_server_submit": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                             ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "simlod_server_poll": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "simlod_server_drain": ([ctypes.c_void_p], ctypes.c_int),
+    "simlod_server_octree": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_void_p),
+    "simlod_server_close": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
+    "simlod_server_counters": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "simlod_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "simlod_last_error": ([], ctypes.c_char_p),
 }
@@ -310,3 +352,177 @@ class Octree:
             self.close()
         except Exception:
             pass
+
+
+class Group:
+    """Batched insertion into several octrees with one pass per call
+    (``simlod_group_*``).  The member ``Octree`` objects stay owned by the
+    caller and must outlive the group."""
+
+    def __init__(self, trees, graph: bool = False, autotune: bool = False):
+        self.trees = list(trees)
+        arr = (ctypes.c_void_p * len(self.trees))(*[t.handle for t in self.trees])
+        flags = (GROUP_GRAPH if graph else 0) | (GROUP_AUTOTUNE if autotune else 0)
+        h = ctypes.c_void_p()
+        _check(lib.simlod_group_create(arr, len(self.trees), flags, ctypes.byref(h)),
+               "simlod_group_create")
+        self.handle = h.value
+
+    def insert(self, batches, stream=None) -> None:
+        """batches[i]: device tensor of 16-byte records for member i (may be
+        empty or None)."""
+        k = len(self.trees)
+        ptrs = (ctypes.c_void_p * k)()
+        ns = (ctypes.c_uint64 * k)()
+        keep = []
+        for i, b in enumerate(batches):
+            if b is None:
+                continue
+            p, n, kk = _points_ptr(b)
+            ptrs[i] = p if n else None
+            ns[i] = n
+            keep.append(kk)
+        _check(lib.simlod_group_insert(self.handle, ptrs, ns, _stream_ptr(stream)),
+               "simlod_group_insert")
+        del keep
+
+    def shape(self):
+        caps = (ctypes.c_uint32 * 4)()
+        state = ctypes.c_uint32()
+        _check(lib.simlod_group_shape(self.handle, caps, ctypes.byref(state)), "simlod_group_shape")
+        return {"caps": list(caps), "tuned": bool(state.value & 1), "graph": bool(state.value & 2)}
+
+    def set_kernel_timing(self, kernels=()) -> None:
+        if kernels == "all":
+            kernels = KERNEL_NAMES
+        mask = 0
+        for k in kernels:
+            mask |= 1 << KERNEL_NAMES.index(k)
+        _check(lib.simlod_group_set_kernel_timing(self.handle, mask),
+               "simlod_group_set_kernel_timing")
+
+    def get_kernel_times(self) -> dict:
+        kt = KernelTimes()
+        _check(lib.simlod_group_get_kernel_times(self.handle, ctypes.byref(kt)),
+               "simlod_group_get_kernel_times")
+        return {name: (int(kt.launches[i]), float(kt.total_ms[i]))
+                for i, name in enumerate(KERNEL_NAMES)}
+
+    def sync(self) -> None:
+        _check(lib.simlod_group_sync(self.handle), "simlod_group_sync")
+
+    def close(self) -> None:
+        if self.handle:
+            destroy_rc = lib.simlod_group_destroy(self.handle)
+            self.handle = None
+            _check(destroy_rc, "simlod_group_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_chunk_capacity(cfg: Config, sample, candidates, stream=None):
+    """Fastest chunk capacity for inserting ``sample`` (device tensor) into a
+    fresh octree of ``cfg``: (best, ms)."""
+    p, n, keep = _points_ptr(sample)
+    arr = (ctypes.c_uint32 * len(candidates))(*candidates)
+    best = ctypes.c_uint32()
+    ms = ctypes.c_double()
+    _check(lib.simlod_tune_chunk_capacity(ctypes.byref(cfg), p if n else None, n, arr,
+                                          len(candidates), _stream_ptr(stream),
+                                          ctypes.byref(best), ctypes.byref(ms)),
+           "simlod_tune_chunk_capacity")
+    del keep
+    return int(best.value), float(ms.value)
+
+
+def config_device_bytes(cfg: Config) -> int:
+    b = ctypes.c_uint64()
+    _check(lib.simlod_config_device_bytes(ctypes.byref(cfg), ctypes.byref(b)),
+           "simlod_config_device_bytes")
+    return int(b.value)
+
+
+class _ServedOctree:
+    """Borrowed view of a served stream's octree (owned by the server)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def snapshot(self, path: int | None = None, nodes_only: bool = False) -> Snapshot:
+        return Snapshot(*snapshot(self.handle, path, nodes_only))
+
+    def stats(self) -> dict:
+        return stats(self.handle)
+
+
+class Server:
+    """Continuous-batching insertion server (``simlod_server_*``)."""
+
+    def __init__(self, max_streams: int, hbm_budget: int, max_per_pass: int = 0, device: int = 0):
+        cfg = ServerConfig(device=device, max_streams=max_streams, hbm_budget=hbm_budget,
+                           max_per_pass=max_per_pass, reserved=0)
+        h = ctypes.c_void_p()
+        _check(lib.simlod_server_create(ctypes.byref(cfg), ctypes.byref(h)), "simlod_server_create")
+        self.handle = h.value
+
+    def open(self, cfg: Config):
+        """Stream id, or None when the server is busy (no slot or budget)."""
+        i = ctypes.c_uint32()
+        rc = lib.simlod_server_open(self.handle, ctypes.byref(cfg), ctypes.byref(i))
+        if rc == ERR_BUSY:
+            return None
+        _check(rc, "simlod_server_open")
+        return int(i.value)
+
+    def submit(self, sid: int, points) -> int:
+        p, n, _ = _points_ptr(points)
+        t = ctypes.c_uint64()
+        _check(lib.simlod_server_submit(self.handle, sid, p if n else None, n, ctypes.byref(t)),
+               "simlod_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(done, latency_ms, status)."""
+        d = ctypes.c_int()
+        ms = ctypes.c_double()
+        rc = lib.simlod_server_poll(self.handle, ticket, ctypes.byref(d), ctypes.byref(ms))
+        return bool(d.value), float(ms.value), int(rc)
+
+    def drain(self) -> None:
+        _check(lib.simlod_server_drain(self.handle), "simlod_server_drain")
+
+    def octree(self, sid: int) -> _ServedOctree:
+        h = lib.simlod_server_octree(self.handle, sid)
+        if not h:
+            raise KeyError(sid)
+        return _ServedOctree(h)
+
+    def close_stream(self, sid: int) -> None:
+        _check(lib.simlod_server_close(self.handle, sid), "simlod_server_close")
+
+    def counters(self) -> dict:
+        out = (ctypes.c_uint64 * 4)()
+        _check(lib.simlod_server_counters(self.handle, out), "simlod_server_counters")
+        return {"passes": out[0], "completed": out[1], "points": out[2], "budget_used": out[3]}
+
+    def close(self) -> None:
+        if self.handle:
+            rc = lib.simlod_server_destroy(self.handle)
+            self.handle = None
+            _check(rc, "simlod_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

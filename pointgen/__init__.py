@@ -22,6 +22,10 @@ shapes, matching sizes in order of magnitude only):
   plus jitter, in scan-like primitive-by-primitive order; batches of 10M
   (seed 2).  Stands in for the terrestrial and photogrammetry scans
   (Endeavor, Chiller, Meroe, the town centre of Retz).
+* ``cloud_set`` -- 64 independent clouds, sizes log-uniform in 100k..50M,
+  each an aerial heightfield or a dense building scan chosen by the seed
+  (seed 3); each is cut into 10 batches and step s inserts batch s of every
+  cloud.
 """
 
 from __future__ import annotations
@@ -120,6 +124,36 @@ def dense_scan(n: int = 1_000_000_000, seed: int = 2, threads: int | None = None
     rc = _load().pg_dense_scan(out.ctypes.data, n, seed, threads or _threads())
     if rc != 0:
         raise RuntimeError(f"pg_dense_scan failed ({rc})")
+    return out
+
+
+AERIAL_CUBE = ((0.0, 0.0, 0.0), 1024.0)
+DENSE_CUBE = ((0.0, 0.0, 0.0), 64.0)
+
+
+def cloud_set(count: int = 64, seed: int = 3, lo: float = 1e5, hi: float = 5e7,
+              scale: float = 1.0):
+    """Independent clouds of uneven size for batched insertion: sizes
+    log-uniform in [lo, hi] (times ``scale``), each one an aerial
+    heightfield or a dense building scan chosen by the seed.
+
+    Returns a list of dicts: kind, points, root_min, root_size, seed."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), count)) * scale
+    kinds = rng.integers(0, 2, count)
+    out = []
+    for i in range(count):
+        n = max(1, int(sizes[i]))
+        s = seed * 1000 + i
+        if kinds[i] == 0:
+            pts = aerial(n, seed=s, order="morton_shuffled", batch=max(1, n // 10))
+            mn, size = AERIAL_CUBE
+            kind = "aerial"
+        else:
+            pts = dense_scan(n, seed=s)
+            mn, size = DENSE_CUBE
+            kind = "dense"
+        out.append(dict(kind=kind, points=pts, root_min=mn, root_size=size, seed=s))
     return out
 
 

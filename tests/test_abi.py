@@ -18,7 +18,8 @@ HEADER = os.path.join(ROOT, "include", "simlod.h")
 
 def _declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(simlod_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:int|const char\*|simlod_octree\*)\s+(simlod_\w+)\s*\(",
+                                 src, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -49,6 +50,7 @@ def test_struct_layouts_match_header(simlod, tmp_path):
         "simlod_snapshot_buffers": simlod.SnapshotBuffers,
         "simlod_stats_data": simlod.StatsData,
         "simlod_kernel_times": simlod.KernelTimes,
+        "simlod_server_config": simlod.ServerConfig,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "simlod.h"', "int main(void){"]
     for cname, ct in structs.items():
@@ -110,10 +112,20 @@ def test_null_arguments(simlod):
     assert simlod.lib.simlod_sync(None) == simlod.ERR_INVALID_ARGUMENT
     assert simlod.lib.simlod_destroy(None) == simlod.OK
     assert simlod.lib.simlod_default_config(None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_group_create(None, 0, 0, None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_group_insert(None, None, None, None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_group_sync(None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_group_shape(None, None, None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_group_destroy(None) == simlod.OK
+    assert simlod.lib.simlod_server_create(None, None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_server_destroy(None) == simlod.OK
+    assert simlod.lib.simlod_server_drain(None) == simlod.ERR_INVALID_ARGUMENT
+    assert simlod.lib.simlod_tune_chunk_capacity(None, None, 0, None, 0, None, None,
+                                                 None) == simlod.ERR_INVALID_ARGUMENT
 
 
 def test_status_strings(simlod):
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         s = simlod.status_string(code)
         assert s and s != "unknown status"
     assert simlod.status_string(-99) == "unknown status"

@@ -1,0 +1,156 @@
+"""Serving (simlod_server_*): continuous batching of insertion requests.
+
+Requests of several streams arrive concurrently (one submitting thread per
+stream, random sizes and gaps); each stream's octree must equal the
+oracle's octree of that stream's points alone, bit for bit -- the same
+alone and in the mix -- in the batched form and in the unbatched
+(one request per pass) form.
+"""
+
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import POINT_DTYPE, LodConfig, assert_trees_equal
+from oracle import definition as O1
+from oracle.canonical import CanonicalTree
+from tests.gpu_util import log, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_03567_amd import simlod  # noqa: F401  (fails loudly if not built)
+
+
+def _cloud(rng, n):
+    xyz = rng.random((n, 3)) ** rng.choice([1, 3])
+    p = np.zeros(n, dtype=POINT_DTYPE)
+    p["x"], p["y"], p["z"] = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    p["rgba"] = rng.integers(0, 2**32, n, dtype=np.uint32)
+    return p
+
+
+def _simlod_cfg(cfg: LodConfig, max_batch):
+    from paper_2310_03567_amd import simlod
+
+    return simlod.make_config(root_min=cfg.root_min, root_size=cfg.root_size,
+                              leaf_capacity=cfg.leaf_capacity, grid_bits=cfg.grid_bits,
+                              max_depth=cfg.max_depth, chunk_capacity=cfg.chunk_capacity,
+                              max_nodes=1 << 17, arena_bytes=256 << 20, max_batch=max_batch,
+                              spill_capacity=1 << 19, backlog_capacity=1 << 19)
+
+
+def _serve(streams, max_per_pass, seed):
+    from paper_2310_03567_amd import simlod
+
+    with simlod.Server(max_streams=8, hbm_budget=64 << 30, max_per_pass=max_per_pass) as sv:
+        ids = [sv.open(_simlod_cfg(cfg, 40_000)) for cfg, _ in streams]
+        assert None not in ids
+        devs = [to_device(p) for _, p in streams]
+        tickets = [[] for _ in streams]
+        errors = []
+
+        def client(k):
+            try:
+                rng = np.random.default_rng(seed + k)
+                n = len(streams[k][1])
+                a = 0
+                while a < n:
+                    b = min(n, a + int(rng.integers(1, 40_000)))
+                    tickets[k].append(sv.submit(ids[k], devs[k][a * 16:b * 16]))
+                    a = b
+                    time.sleep(float(rng.random()) * 0.002)
+            except Exception as e:  # reported below
+                errors.append(e)
+
+        th = [threading.Thread(target=client, args=(k,)) for k in range(len(streams))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        sv.drain()
+        assert not errors, (errors, [sv.octree(i).stats()["status_bits"] for i in ids])
+        lat = []
+        for ts in tickets:
+            for t in ts:
+                done, ms, rc = sv.poll(t)
+                assert done and rc == simlod.OK
+                lat.append(ms)
+        got = []
+        for i in ids:
+            s = sv.octree(i).snapshot()
+            got.append(CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys))
+        counters = sv.counters()
+    return got, lat, counters
+
+
+@pytest.mark.parametrize("max_per_pass", [0, 1])
+def test_served_streams_equal_their_oracle(max_per_pass):
+    rng = np.random.default_rng(31)
+    streams = []
+    for k in range(6):
+        cfg = LodConfig(leaf_capacity=int(rng.choice([20, 50, 500])), grid_bits=int(rng.integers(1, 5)),
+                        max_depth=int(rng.integers(4, 10)), chunk_capacity=int(rng.choice([3, 64, 1000])))
+        streams.append((cfg, _cloud(rng, int(rng.integers(1_000, 150_000)))))
+    log(f"case: served, 6 streams, max_per_pass={max_per_pass}")
+    got, lat, counters = _serve(streams, max_per_pass, seed=32)
+    for k, ((cfg, p), t) in enumerate(zip(streams, got)):
+        assert_trees_equal(t, O1.build(p, cfg), f"stream {k} n={len(p)}")
+    assert counters["completed"] == len(lat) and counters["points"] == sum(len(p) for _, p in streams)
+    if max_per_pass == 1:
+        assert counters["passes"] == len(lat)
+    log(f"passes {counters['passes']} requests {len(lat)} p50 {np.percentile(lat, 50):.3f} ms")
+
+
+def test_admission_by_budget_and_slots():
+    from paper_2310_03567_amd import simlod
+
+    cfg = _simlod_cfg(LodConfig(leaf_capacity=50, grid_bits=3, max_depth=8), 10_000)
+    need = simlod.config_device_bytes(cfg)
+    log("case: server admission")
+    with simlod.Server(max_streams=3, hbm_budget=2 * need + need // 2) as sv:
+        a = sv.open(cfg)
+        b = sv.open(cfg)
+        assert a is not None and b is not None
+        assert sv.open(cfg) is None  # budget
+        assert sv.counters()["budget_used"] == 2 * need
+        sv.close_stream(a)
+        c = sv.open(cfg)
+        assert c == a  # the freed slot and budget are reused
+        unused = ({0, 1, 2} - {b, c}).pop()
+        with pytest.raises(simlod.SimlodError):
+            sv.submit(unused, to_device(_cloud(np.random.default_rng(1), 10)))  # not open
+
+
+def test_overflowing_stream_fails_alone():
+    from paper_2310_03567_amd import simlod
+
+    rng = np.random.default_rng(33)
+    good_cfg = LodConfig(leaf_capacity=50, grid_bits=3, max_depth=8)
+    p, q = _cloud(rng, 30_000), _cloud(rng, 30_000)
+    log("case: server overflow isolation")
+    with simlod.Server(max_streams=4, hbm_budget=64 << 30) as sv:
+        bad_cfg = _simlod_cfg(good_cfg, 40_000)
+        bad_cfg.max_nodes = 17
+        bad = sv.open(bad_cfg)
+        good = sv.open(_simlod_cfg(good_cfg, 40_000))
+        dp, dq = to_device(p), to_device(q)
+        tb = [sv.submit(bad, dp[i * 16:(i + 10_000) * 16]) for i in range(0, 30_000, 10_000)]
+        tg = [sv.submit(good, dq[i * 16:(i + 10_000) * 16]) for i in range(0, 30_000, 10_000)]
+        sv.drain()
+        assert sv.poll(tb[0])[2] == simlod.ERR_CAPACITY
+        assert all(sv.poll(t)[2] in (simlod.ERR_CAPACITY, simlod.ERR_POISONED) for t in tb)
+        assert all(sv.poll(t)[2] == simlod.OK for t in tg)
+        s = sv.octree(good).snapshot()
+        assert_trees_equal(CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys),
+                           O1.build(q, good_cfg))
