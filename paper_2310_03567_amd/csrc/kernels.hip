@@ -43,7 +43,8 @@
 
 namespace simlod {
 
-constexpr u32 kWG = 256;
+constexpr u32 kWG = 256;  // 4 wavefronts; the LDS tables and scans assume it
+static_assert(kWG == 256, "workgroup scans and LDS tables are laid out for 4 wavefronts");
 constexpr u32 kLdsBits = 11;
 constexpr u32 kLds = 1u << kLdsBits;
 constexpr u32 kMaxProbe = 4096;
@@ -458,33 +459,36 @@ __global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, 
 }
 
 // Exclusive prefix sum of a[0..n) in LDS by one workgroup; returns the total.
+// Each thread sums a contiguous chunk; the 256 chunk sums are scanned with
+// wavefront shuffles (4 wavefronts, their totals combined through LDS).
 // part: LDS scratch of kWG + 1 entries.
 __device__ u32 wg_exclusive_scan(u32* a, u32 n, u32* part) {
     const u32 tid = threadIdx.x;
+    const u32 lane = lane_id();
+    const u32 wave = tid >> 6;
     const u32 per = (n + kWG - 1u) / kWG;
     const u32 lo = min(tid * per, n), hi = min(lo + per, n);
     u32 sum = 0u;
     for (u32 i = lo; i < hi; ++i) sum += a[i];
-    part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        u32 run = 0u;
-        for (u32 i = 0; i < kWG; ++i) {
-            const u32 v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        part[kWG] = run;
+    u32 v = sum;  // inclusive scan within the wavefront
+#pragma unroll
+    for (u32 o = 1; o < 64u; o <<= 1) {
+        const u32 y = __shfl_up(v, o);
+        if (lane >= o) v += y;
     }
+    if (lane == 63u) part[wave] = v;  // wavefront totals
     __syncthreads();
-    u32 run = part[tid];
+    u32 before = 0u;
+    for (u32 w = 0; w < wave; ++w) before += part[w];
+    const u32 total = part[0] + part[1] + part[2] + part[3];
+    u32 run = before + v - sum;  // exclusive prefix of this thread's chunk
     for (u32 i = lo; i < hi; ++i) {
-        const u32 v = a[i];
+        const u32 x = a[i];
         a[i] = run;
-        run += v;
+        run += x;
     }
-    __syncthreads();
-    return part[kWG];
+    __syncthreads();  // part[] and a[] complete before anyone reuses them
+    return total;
 }
 
 // Index layout of one pending root's virtual subtree in the build kernel:
@@ -1138,6 +1142,10 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         }
         le = __shfl(le, r.head);
         r0 = __shfl(r0, r.head) + r.rank;
+        // the leaf's chunk count and chunk table (written by the allocation
+        // kernel) load now, so that only the chunk id waits for the slot
+        const u32 nch = valid ? t.nchunks[leaf] : 0u;
+        const u32* ltab = valid ? table_of(t, leaf) : nullptr;
         const u32 nx = next_tile(tile, ntiles);
         const u32 cn = nx == kNone ? kNone : member_of(s_pre, count, nx);
         __syncthreads();
@@ -1157,8 +1165,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
             const u32 ci = slot / t.C;
-            if (ci < t.nchunks[leaf]) {
-                const u32 cbk = table_of(t, leaf)[ci];
+            if (ci < nch) {
+                const u32 cbk = ltab[ci];
                 const u32 o = slot - ci * t.C;
                 chunk_recs(t, cbk)[o] = rec;
                 chunk_keys(t, cbk)[o] = key;
@@ -1242,6 +1250,15 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
         }
         ne = __shfl(ne, r.head);
         r0 = __shfl(r0, r.head) + r.rank;
+        // the node's geometry, chunk count and chunk table load now
+        uint4 g = make_uint4(0u, 0u, 0u, 0u);
+        u32 nch = 0u;
+        const u32* ntab = nullptr;
+        if (valid) {
+            g = t.geo[node];
+            nch = t.nchunks[node];
+            ntab = table_of(t, node);
+        }
         // grid bits: OR per word in LDS
         if (valid) {
             const u64 wkey = ((u64)node << 32) | (lin >> 5);
@@ -1275,7 +1292,6 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
         __syncthreads();
         if (valid) {
             const u32 slot = s_nbase[ne] + r0;
-            const uint4 g = t.geo[node];
             const u32 d = g.w;
             const u32 shift = t.Dmax - d;
             const u32 cx = lin & rmask, cy = (lin >> t.r) & rmask, cz = lin >> (2u * t.r);
@@ -1285,8 +1301,8 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             v.z = __float_as_uint(cell_centre((g.z >> shift) + cz, t.mn[2], t.size, t.r, d));
             v.w = (u32)val;
             const u32 ci = slot / t.C;
-            if (ci < t.nchunks[node]) {
-                const u32 cb = table_of(t, node)[ci];
+            if (ci < nch) {
+                const u32 cb = ntab[ci];
                 const u32 o = slot - ci * t.C;
                 chunk_recs(t, cb)[o] = v;
                 chunk_keys(t, cb)[o] = (u32)(val >> 32);
