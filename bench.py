@@ -248,76 +248,91 @@ def run_served(args):
     slots = 16
     cfgs = [cloud_config(c, 5_000_000) for c in clouds]
 
-    def serve(offered_pps, max_per_pass, seed):
+    def serve(sv, offered_pps, seed):
         rate = offered_pps / slots / mean_req  # requests/s per slot
         rng = np.random.default_rng(seed)
-        lat, pending = [], []
-        with simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=max_per_pass) as sv:
-            queue = list(range(len(clouds)))
-            active = {}  # slot index -> [cloud, next request, stream id, next arrival, tickets]
-            start = time.perf_counter()
+        lat = []
+        c0 = sv.counters()
+        queue = list(range(len(clouds)))
+        active = {}  # slot index -> [cloud, next request, stream id, next arrival, tickets]
+        start = time.perf_counter()
+        for k in range(slots):
+            active[k] = None
+        done_points = 0
+        while True:
+            now = time.perf_counter() - start
             for k in range(slots):
-                active[k] = None
-            done_points = 0
-            while True:
-                now = time.perf_counter() - start
-                for k in range(slots):
-                    st = active[k]
-                    if st is None and queue:
-                        sid = sv.open(cfgs[queue[0]])
-                        if sid is not None:
-                            ci = queue.pop(0)
-                            active[k] = [ci, 0, sid, now + rng.exponential(1.0 / rate), []]
-                        continue
-                    if st is None:
-                        continue
-                    ci, r, sid, t_next, tickets = st
-                    cuts = reqs[ci]
-                    while r < len(cuts) - 1 and t_next <= now:
-                        b = devs[ci][cuts[r] * 16:cuts[r + 1] * 16]
-                        tickets.append(sv.submit(sid, b))
-                        r += 1
-                        t_next += rng.exponential(1.0 / rate)
-                    st[1], st[3] = r, t_next
-                    if r == len(cuts) - 1 and all(sv.poll(t)[0] for t in tickets[-1:]):
-                        for t in tickets:
-                            d, ms, rc = sv.poll(t)
-                            if not d or rc != simlod.OK:
-                                raise RuntimeError(f"request failed ({rc})")
-                            lat.append(ms)
-                        done_points += cuts[-1]
-                        sv.close_stream(sid)
-                        active[k] = None
-                if not queue and all(v is None for v in active.values()):
-                    break
-                time.sleep(0.0002)
-            el = time.perf_counter() - start
-            c = sv.counters()
+                st = active[k]
+                if st is None and queue:
+                    sid = sv.open(cfgs[queue[0]])
+                    if sid is not None:
+                        ci = queue.pop(0)
+                        active[k] = [ci, 0, sid, now + rng.exponential(1.0 / rate), []]
+                    continue
+                if st is None:
+                    continue
+                ci, r, sid, t_next, tickets = st
+                cuts = reqs[ci]
+                while r < len(cuts) - 1 and t_next <= now:
+                    b = devs[ci][cuts[r] * 16:cuts[r + 1] * 16]
+                    tickets.append(sv.submit(sid, b))
+                    r += 1
+                    t_next += rng.exponential(1.0 / rate)
+                st[1], st[3] = r, t_next
+                if r == len(cuts) - 1 and all(sv.poll(t)[0] for t in tickets[-1:]):
+                    for t in tickets:
+                        d, ms, rc = sv.poll(t)
+                        if not d or rc != simlod.OK:
+                            raise RuntimeError(f"request failed ({rc})")
+                        lat.append(ms)
+                    done_points += cuts[-1]
+                    sv.close_stream(sid)
+                    active[k] = None
+            if not queue and all(v is None for v in active.values()):
+                break
+            time.sleep(0.0002)
+        el = time.perf_counter() - start
+        sv.wait_closed()
+        c = sv.counters()
         lat = np.array(lat)
+        passes = int(c["passes"] - c0["passes"])
         return {"offered_points_per_s": round(offered_pps, 1),
                 "achieved_points_per_s": round(done_points / el, 1),
-                "requests": int(len(lat)), "passes": int(c["passes"]),
-                "requests_per_pass": round(len(lat) / max(c["passes"], 1), 2),
+                "requests": int(len(lat)), "passes": passes,
+                "requests_per_pass": round(len(lat) / max(passes, 1), 2),
                 "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                 "seconds": round(el, 3)}
 
-    offered = args.offered * 1e9
-    serve(offered, 0, seed=40)  # warm-up run
-    batched = serve(offered, 0, seed=41)
-    plain = serve(offered, 1, seed=41)
+    loads = [float(x) * 1e9 for x in str(args.offered).split(",")]
+    runs = {}
+    for form, per_pass in (("batched", 0), ("unbatched", 1)):
+        # one server per form; its warm-up run allocates the octrees, which
+        # the timed runs then reuse from the server's pool
+        sv = simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=per_pass)
+        serve(sv, loads[0], seed=40)
+        runs[form] = [serve(sv, offered, seed=41 + k) for k, offered in enumerate(loads)]
+        sv.close()
+    sweep = []
+    for k, offered in enumerate(loads):
+        b, u = runs["batched"][k], runs["unbatched"][k]
+        sweep.append({"batched": b, "unbatched": u})
+        log(f"offered {offered / 1e9:.2f} G/s: batched {b['achieved_points_per_s'] / 1e9:.2f} G/s "
+            f"p99 {b['latency_ms_p99']} ms; unbatched {u['achieved_points_per_s'] / 1e9:.2f} G/s "
+            f"p99 {u['latency_ms_p99']} ms")
+    top = sweep[-1]["batched"]
     result = {
         "metric": "served insertion: points/sec with p50/p99 update latency",
-        "value": batched["achieved_points_per_s"], "unit": "points/s", "n_gpus": 1,
-        "steps": batched["requests"], "warmup": 1,
-        "ms_per_step": round(batched["seconds"] * 1e3 / max(batched["requests"], 1), 4),
-        "update_ms_p50": batched["latency_ms_p50"], "update_ms_p99": batched["latency_ms_p99"],
+        "value": top["achieved_points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "steps": top["requests"], "warmup": 1,
+        "ms_per_step": round(top["seconds"] * 1e3 / max(top["requests"], 1), 4),
+        "update_ms_p50": top["latency_ms_p50"], "update_ms_p99": top["latency_ms_p99"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "16 stream slots, 20 clouds of 10M..200M points, requests of "
                                "50k..5M points, Poisson arrivals, 200 GB admission budget",
                    "points": total, "requests": nreq},
-        "batched": batched, "unbatched": plain,
+        "sweep": sweep,
     }
     print(json.dumps(result), flush=True)
 
@@ -348,8 +363,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="aerial",
                     choices=sorted(WORKLOADS) + ["batched", "served"])
-    ap.add_argument("--offered", type=float, default=1.5,
-                    help="served workload: offered load in G points/s over all streams")
+    ap.add_argument("--offered", default="1.5,6,24",
+                    help="served workload: offered loads in G points/s over all streams "
+                         "(comma-separated; the last one is reported as value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

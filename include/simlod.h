@@ -375,8 +375,10 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out);
 int simlod_config_device_bytes(const simlod_config* cfg, uint64_t* bytes);
 
 /* Admits an octree with configuration *cfg (its device must be the
- * server's): BUSY when no stream slot is free or its device bytes would
- * exceed the budget left; *id names the stream. */
+ * server's; arena_bytes set): reuses a pooled octree when one fits (see
+ * simlod_server_close), else allocates one; BUSY when no stream slot is free
+ * or its device bytes would exceed the budget even with the pool released;
+ * *id names the stream. */
 int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id);
 
 /* Queues the insertion of pts[0..n) (16-byte-aligned device memory that the
@@ -398,8 +400,18 @@ int simlod_server_drain(simlod_server* sv);
  * have completed (owned by the server; NULL if id is not open). */
 simlod_octree* simlod_server_octree(simlod_server* sv, uint32_t id);
 
-/* Waits for the stream's requests, destroys its octree, frees its budget. */
+/* Closes a stream and returns at once: no more submissions; once its
+ * queued requests have completed its slot frees up and its octree joins the
+ * server's pool.  Pooled octrees keep their device memory (and budget): a
+ * later open reuses the smallest one whose buffers fit the new
+ * configuration, reconfigured and reset on the server's stream, so a running
+ * server neither allocates nor frees device memory (either synchronizes the
+ * device and stalls the passes).  An open that fits no pooled octree and
+ * exceeds the budget releases pooled octrees, largest first. */
 int simlod_server_close(simlod_server* sv, uint32_t id);
+
+/* Blocks until every closed stream's slot has been freed. */
+int simlod_server_wait_closed(simlod_server* sv);
 
 /* Counters: passes launched, requests completed, points inserted, device
  * bytes held by open octrees. */

@@ -56,6 +56,7 @@ struct simlod_octree {
     Timing tm;
     u64 dev_bytes = 0;     // device memory held
     u64* dry = nullptr;    // set: dalloc only adds up sizes
+    simlod_config alloc_cfg{};  // the configuration its buffers were sized for
 };
 
 namespace {
@@ -323,6 +324,67 @@ int sync_handle(simlod_octree* h) {
 
 // Every device buffer of an octree (the same sequence sizes a configuration
 // when h->dry is set).  arena_bytes: 0 = 90% of the free memory.
+// Sets every scalar of the handle's DevTree (capacities, geometry, derived
+// sizes) from *cfg; the buffer pointers stay.  arena_bytes: the arena size
+// to use.
+static void configure_tree(simlod_octree* h, const simlod_config* cfg, u64 arena_bytes) {
+    DevTree& t = h->t;
+    h->cfg = *cfg;
+    h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
+    t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
+    t.max_nodes = cfg->max_nodes;
+    t.hist_cap = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
+    t.spill_cap = (u32)cfg->spill_capacity;
+    t.active_cap = (u32)(cfg->max_batch + cfg->spill_capacity);
+    t.hmask = (u32)(h->hash_entries - 1);
+    t.claim_cap = (u32)cfg->backlog_capacity;
+    const u64 chunk_bytes = (u64)cfg->chunk_capacity * 20u + 4u;
+    t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);
+    const u64 cells = 1ull << (3 * cfg->grid_bits);
+    t.grid_words = (u32)std::max<u64>(1, cells / 32);
+    t.grid_blocks = (u32)((t.grid_words * 4ull + kBlockBytes - 1) / kBlockBytes);
+    t.arena_blocks = (u32)std::min<u64>(arena_bytes / kBlockBytes, 0xFFFFFFF0ull);
+    t.pool_cap = t.arena_blocks / t.chunk_blocks + 1;
+    for (int a = 0; a < 3; ++a) t.mn[a] = cfg->root_min[a];
+    t.size = cfg->root_size;
+    t.K = cfg->max_depth + cfg->grid_bits;
+    t.r = cfg->grid_bits;
+    t.R = 1u << cfg->grid_bits;
+    t.Dmax = cfg->max_depth;
+    t.T = cfg->leaf_capacity;
+    t.C = cfg->chunk_capacity;
+    t.scale = (float)(1u << t.K) / cfg->root_size;  // float32 division
+}
+
+// Element counts of every buffer a configuration needs; a handle allocated
+// for A can serve B when each of B's counts is at most A's.
+struct Footprint {
+    u64 v[9];
+};
+
+static Footprint footprint_of(const simlod_config* c) {
+    const u64 chunk_bytes = (u64)c->chunk_capacity * 20u + 4u;
+    const u64 chunk_blocks = (chunk_bytes + kBlockBytes - 1) / kBlockBytes;
+    const u64 arena_blocks = std::min<u64>(c->arena_bytes / kBlockBytes, 0xFFFFFFF0ull);
+    Footprint f;
+    f.v[0] = c->max_nodes;
+    f.v[1] = dir_offset(std::min<u32>(c->max_depth, kDirMaxDepth) + 1u);
+    f.v[2] = c->spill_capacity;
+    f.v[3] = c->hist_capacity ? c->hist_capacity : 8192u;
+    f.v[4] = c->max_batch + c->spill_capacity;
+    f.v[5] = next_pow2(2 * c->backlog_capacity);
+    f.v[6] = c->backlog_capacity * kStripes;
+    f.v[7] = arena_blocks;
+    f.v[8] = arena_blocks / chunk_blocks + 1;
+    return f;
+}
+
+static bool footprint_fits(const Footprint& have, const Footprint& need) {
+    for (int i = 0; i < 9; ++i)
+        if (need.v[i] > have.v[i]) return false;
+    return true;
+}
+
 static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_bytes) {
     DevTree& t = h->t;
     std::memset(&t, 0, sizeof(t));
@@ -419,21 +481,9 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     }
     *h->h_status = 0;
     DevTree& t = h->t;
-    t.max_nodes = cfg->max_nodes;
-    t.hist_cap = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
-    t.spill_cap = (u32)cfg->spill_capacity;
-    t.active_cap = (u32)(cfg->max_batch + cfg->spill_capacity);
-    t.hmask = (u32)(h->hash_entries - 1);
-    t.claim_cap = (u32)cfg->backlog_capacity;
-    for (int a = 0; a < 3; ++a) t.mn[a] = cfg->root_min[a];
-    t.size = cfg->root_size;
-    t.K = cfg->max_depth + cfg->grid_bits;
-    t.r = cfg->grid_bits;
-    t.R = 1u << cfg->grid_bits;
-    t.Dmax = cfg->max_depth;
-    t.T = cfg->leaf_capacity;
-    t.C = cfg->chunk_capacity;
-    t.scale = (float)(1u << t.K) / cfg->root_size;  // float32 division
+    configure_tree(h, cfg, (u64)t.arena_blocks * kBlockBytes);
+    h->alloc_cfg = *cfg;
+    h->alloc_cfg.arena_bytes = (u64)t.arena_blocks * kBlockBytes;
     clear_stale_error();
     hipError_t re = hipMemcpy(h->d_tree, &t, sizeof(DevTree), hipMemcpyHostToDevice);
     if (re != hipSuccess) note_error("device tree copy", re);
@@ -1205,7 +1255,14 @@ struct simlod_server {
     u32* d_status = nullptr;  // kMaxMembers words
     u32* h_status = nullptr;  // pinned, kStatusRing x kMaxMembers
     bool stop = false;
-    std::thread scheduler, completer;
+    std::deque<u32> reap;            // closed slots waiting for their last requests
+    std::condition_variable cv_reap;
+    struct Pooled {
+        simlod_octree* h;
+        u64 bytes;
+    };
+    std::vector<Pooled> pool;        // closed octrees kept for reuse (budget still held)
+    std::thread scheduler, completer, reaper;
 };
 
 namespace {
@@ -1259,6 +1316,7 @@ void server_schedule(simlod_server* sv) {
         std::vector<ServerRequest> reqs = server_pick(sv);
         if (reqs.empty()) {
             sv->cv_done.notify_all();
+            sv->cv_reap.notify_all();
             continue;
         }
         ServerPass* ps = new ServerPass();
@@ -1346,6 +1404,41 @@ void server_complete(simlod_server* sv) {
         delete ps;
         sv->cv_work.notify_all();
         sv->cv_done.notify_all();
+        sv->cv_reap.notify_all();
+    }
+}
+
+// Moves the octrees of closed streams, once their requests have completed,
+// to the pool: device memory is neither freed nor allocated while requests
+// flow (either would synchronize the device and stall the passes); a later
+// open reuses a pooled octree whose buffers are large enough.
+void server_reap(simlod_server* sv) {
+    (void)hipSetDevice(sv->cfg.device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_reap.wait(lk, [&] {
+            if (sv->stop && sv->reap.empty()) return true;
+            for (u32 id : sv->reap) {
+                const ServerSlot& sl = sv->slots[id];
+                if (sl.queue.empty() && sl.inflight == 0) return true;
+            }
+            return false;
+        });
+        if (sv->stop && sv->reap.empty()) return;
+        u32 id = kNone;
+        for (auto it = sv->reap.begin(); it != sv->reap.end(); ++it) {
+            const ServerSlot& sl = sv->slots[*it];
+            if (sl.queue.empty() && sl.inflight == 0) {
+                id = *it;
+                sv->reap.erase(it);
+                break;
+            }
+        }
+        if (id == kNone) continue;
+        ServerSlot& sl = sv->slots[id];
+        sv->pool.push_back({sl.h, sl.bytes});
+        sl = ServerSlot{};
+        sv->cv_done.notify_all();
     }
 }
 
@@ -1397,6 +1490,7 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
     }
     sv->scheduler = std::thread(server_schedule, sv);
     sv->completer = std::thread(server_complete, sv);
+    sv->reaper = std::thread(server_reap, sv);
     *out = sv;
     return SIMLOD_OK;
 }
@@ -1406,24 +1500,80 @@ int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id
     u64 bytes = 0;
     int rc = simlod_config_device_bytes(cfg, &bytes);
     if (rc) return rc;
+    const Footprint need = footprint_of(cfg);
     u32 slot = 0;
+    simlod_octree* reuse = nullptr;
+    u64 reuse_bytes = 0;
+    std::vector<simlod_octree*> evict;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         while (slot < sv->slots.size() &&
                (sv->slots[slot].open || sv->slots[slot].opening || sv->slots[slot].closing))
             ++slot;
-        if (slot == sv->slots.size() || sv->budget_used + bytes > sv->cfg.hbm_budget)
-            return SIMLOD_ERR_BUSY;
+        if (slot == sv->slots.size()) return SIMLOD_ERR_BUSY;
+        // the smallest pooled octree whose buffers are large enough
+        size_t best = sv->pool.size();
+        for (size_t i = 0; i < sv->pool.size(); ++i)
+            if (footprint_fits(footprint_of(&sv->pool[i].h->alloc_cfg), need) &&
+                (best == sv->pool.size() || sv->pool[i].bytes < sv->pool[best].bytes))
+                best = i;
+        if (best < sv->pool.size()) {
+            reuse = sv->pool[best].h;
+            reuse_bytes = sv->pool[best].bytes;
+            sv->pool.erase(sv->pool.begin() + (long)best);
+        } else {
+            // make room by releasing pooled octrees, largest first
+            std::sort(sv->pool.begin(), sv->pool.end(),
+                      [](const simlod_server::Pooled& a, const simlod_server::Pooled& b) {
+                          return a.bytes < b.bytes;
+                      });
+            while (sv->budget_used + bytes > sv->cfg.hbm_budget && !sv->pool.empty()) {
+                evict.push_back(sv->pool.back().h);
+                sv->budget_used -= sv->pool.back().bytes;
+                sv->pool.pop_back();
+            }
+            if (sv->budget_used + bytes > sv->cfg.hbm_budget) {
+                for (simlod_octree* h : evict) (void)simlod_destroy(h);
+                return SIMLOD_ERR_BUSY;
+            }
+            sv->budget_used += bytes;
+        }
         sv->slots[slot].opening = true;
-        sv->budget_used += bytes;
     }
-    simlod_octree* h = nullptr;
-    rc = simlod_create(cfg, &h);
+    for (simlod_octree* h : evict) (void)simlod_destroy(h);
+    simlod_octree* h = reuse;
+    if (reuse) {
+        // same buffers, new configuration; the reset is ordered on the
+        // server's stream before the stream's first pass
+        DeviceGuard guard(sv->cfg.device);
+        configure_tree(h, cfg, cfg->arena_bytes);
+        hipError_t e = hipMemcpyAsync(h->d_tree, &h->t, sizeof(DevTree), hipMemcpyHostToDevice,
+                                      sv->stream);
+        if (e == hipSuccess) e = launch_reset(h->t, h->hash_entries, sv->stream);
+        h->total_points = 0;
+        h->passes = 0;
+        h->poisoned = 0;
+        h->sticky = SIMLOD_OK;
+        h->status_pending = false;
+        h->last_stream = sv->stream;
+        if (e != hipSuccess) {
+            note_error("pooled octree reset", e);
+            clear_stale_error();
+            rc = SIMLOD_ERR_HIP;
+        }
+        bytes = reuse_bytes;
+    } else {
+        rc = simlod_create(cfg, &h);
+    }
     std::lock_guard<std::mutex> lk(sv->mu);
     ServerSlot& sl = sv->slots[slot];
     sl.opening = false;
     if (rc) {
-        sv->budget_used -= bytes;
+        if (h) {
+            sv->pool.push_back({h, bytes});
+        } else {
+            sv->budget_used -= bytes;
+        }
         return rc;
     }
     sl.h = h;
@@ -1491,23 +1641,26 @@ simlod_octree* simlod_server_octree(simlod_server* sv, uint32_t id) {
 
 int simlod_server_close(simlod_server* sv, uint32_t id) {
     if (!sv) return SIMLOD_ERR_INVALID_ARGUMENT;
-    simlod_octree* h = nullptr;
-    {
-        std::unique_lock<std::mutex> lk(sv->mu);
-        if (id >= sv->slots.size() || !sv->slots[id].open || sv->slots[id].closing)
-            return SIMLOD_ERR_INVALID_ARGUMENT;
-        ServerSlot& sl = sv->slots[id];
-        sl.closing = true;
-        sv->cv_work.notify_all();
-        sv->cv_done.wait(lk, [&] { return sl.queue.empty() && sl.inflight == 0; });
-        h = sl.h;
-    }
-    const int rc = simlod_destroy(h);
     std::lock_guard<std::mutex> lk(sv->mu);
-    ServerSlot& sl = sv->slots[id];
-    sv->budget_used -= sl.bytes;
-    sl = ServerSlot{};
-    return rc;
+    if (id >= sv->slots.size() || !sv->slots[id].open || sv->slots[id].closing)
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    sv->slots[id].closing = true;
+    sv->reap.push_back(id);
+    sv->cv_work.notify_all();
+    sv->cv_reap.notify_all();
+    return SIMLOD_OK;
+}
+
+int simlod_server_wait_closed(simlod_server* sv) {
+    if (!sv) return SIMLOD_ERR_INVALID_ARGUMENT;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_reap.notify_all();
+    sv->cv_done.wait(lk, [&] {
+        for (const ServerSlot& sl : sv->slots)
+            if (sl.closing) return false;
+        return true;
+    });
+    return SIMLOD_OK;
 }
 
 int simlod_server_counters(simlod_server* sv, uint64_t out[4]) {
@@ -1529,13 +1682,17 @@ int simlod_server_destroy(simlod_server* sv) {
     }
     sv->cv_work.notify_all();
     sv->cv_retire.notify_all();
+    sv->cv_reap.notify_all();
     sv->scheduler.join();
     sv->completer.join();
+    sv->reaper.join();
     DeviceGuard guard(sv->cfg.device);
     (void)hipStreamSynchronize(sv->stream);
     int rc = SIMLOD_OK;
     for (ServerSlot& sl : sv->slots)
         if (sl.h && simlod_destroy(sl.h) != SIMLOD_OK) rc = SIMLOD_ERR_HIP;
+    for (auto& p : sv->pool)
+        if (simlod_destroy(p.h) != SIMLOD_OK) rc = SIMLOD_ERR_HIP;
     for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(sv->stream);
     (void)hipFree(sv->d_table);

@@ -137,6 +137,7 @@ EXPORTS = {
     "simlod_server_drain": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_server_octree": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_void_p),
     "simlod_server_close": ([ctypes.c_void_p, ctypes.c_uint32], ctypes.c_int),
+    "simlod_server_wait_closed": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_server_counters": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "simlod_server_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -508,7 +509,11 @@ class Server:
         return _ServedOctree(h)
 
     def close_stream(self, sid: int) -> None:
+        """Closes at once; the octree is destroyed in the background."""
         _check(lib.simlod_server_close(self.handle, sid), "simlod_server_close")
+
+    def wait_closed(self) -> None:
+        _check(lib.simlod_server_wait_closed(self.handle), "simlod_server_wait_closed")
 
     def counters(self) -> dict:
         out = (ctypes.c_uint64 * 4)()

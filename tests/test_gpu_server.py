@@ -125,6 +125,7 @@ def test_admission_by_budget_and_slots():
         assert sv.open(cfg) is None  # budget
         assert sv.counters()["budget_used"] == 2 * need
         sv.close_stream(a)
+        sv.wait_closed()
         c = sv.open(cfg)
         assert c == a  # the freed slot and budget are reused
         unused = ({0, 1, 2} - {b, c}).pop()
@@ -154,3 +155,43 @@ def test_overflowing_stream_fails_alone():
         s = sv.octree(good).snapshot()
         assert_trees_equal(CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys),
                            O1.build(q, good_cfg))
+
+
+def test_pooled_octree_reused_with_another_configuration():
+    """A closed stream's octree is reused for a smaller configuration with a
+    different geometry; the new stream's octree is still exactly the
+    oracle's, and no device memory is added to the budget."""
+    from paper_2310_03567_amd import simlod
+
+    rng = np.random.default_rng(35)
+    big = LodConfig(leaf_capacity=40, grid_bits=4, max_depth=9, chunk_capacity=100)
+    # different geometry and capacities; chunks no smaller (smaller chunks
+    # need a longer chunk pool than the pooled octree has)
+    small = LodConfig(root_min=(-2.0, 1.0, 0.5), root_size=3.0, leaf_capacity=15, grid_bits=2,
+                      max_depth=7, chunk_capacity=250)
+    p = _cloud(rng, 40_000)
+    q = _cloud(rng, 25_000)
+    q_xyz = np.stack([q["x"], q["y"], q["z"]], axis=1) * np.float32(3.0) + np.array(
+        [-2.0, 1.0, 0.5], dtype=np.float32)
+    q["x"], q["y"], q["z"] = q_xyz[:, 0], q_xyz[:, 1], q_xyz[:, 2]
+    log("case: server pool reuse")
+    with simlod.Server(max_streams=2, hbm_budget=64 << 30) as sv:
+        a = sv.open(_simlod_cfg(big, 40_000))
+        dp = to_device(p)
+        sv.submit(a, dp)
+        sv.drain()
+        used = sv.counters()["budget_used"]
+        sv.close_stream(a)
+        sv.wait_closed()
+        small_cfg = _simlod_cfg(small, 20_000)
+        small_cfg.arena_bytes = 64 << 20
+        b = sv.open(small_cfg)
+        assert sv.counters()["budget_used"] == used  # the pooled octree, no new memory
+        dq = to_device(q)
+        t1 = sv.submit(b, dq[:12_000 * 16])
+        t2 = sv.submit(b, dq[12_000 * 16:])
+        sv.drain()
+        assert sv.poll(t1)[2] == simlod.OK and sv.poll(t2)[2] == simlod.OK
+        s = sv.octree(b).snapshot()
+        assert_trees_equal(CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys),
+                           O1.build(q, small))
