@@ -404,8 +404,7 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.zero_list, N) &&
               dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
-              dalloc(h, &t.amask[1], work) && dalloc(h, &t.htag, h->hash_entries) &&
-              dalloc(h, &t.hval, h->hash_entries) &&
+              dalloc(h, &t.amask[1], work) && dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
               dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 1);
     const u32 C = cfg->chunk_capacity;

@@ -801,12 +801,12 @@ __global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 v
 __device__ __forceinline__ bool claim_cell(const DevTree& t, u64 tag, u64 val, u32& slot) {
     u32 h = (u32)mix64(tag) & t.hmask;
     for (u32 p = 0; p < kMaxProbe; ++p) {
-        u64 cur = t.htag[h];
+        u64 cur = *claim_tag(t, h);
         if (cur == kEmptyTag)
-            cur = atomicCAS((unsigned long long*)&t.htag[h], (unsigned long long)kEmptyTag,
+            cur = atomicCAS((unsigned long long*)claim_tag(t, h), (unsigned long long)kEmptyTag,
                             (unsigned long long)tag);
         if (cur == kEmptyTag || cur == tag) {
-            atomicMin((unsigned long long*)&t.hval[h], (unsigned long long)val);
+            atomicMin((unsigned long long*)claim_val(t, h), (unsigned long long)val);
             slot = h;
             return cur == kEmptyTag;
         }
@@ -944,7 +944,7 @@ __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cv
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k)
         b.cur[k] = b.tg[k] != kEmptyTag
-                       ? atomicCAS((unsigned long long*)&t.htag[b.hh[k]],
+                       ? atomicCAS((unsigned long long*)claim_tag(t, b.hh[k]),
                                    (unsigned long long)kEmptyTag, (unsigned long long)b.tg[k])
                        : 0ull;
 }
@@ -958,7 +958,7 @@ __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch
         bool fresh;
         u32 hslot = b.hh[k];
         if (b.cur[k] == kEmptyTag || b.cur[k] == b.tg[k]) {
-            atomicMin((unsigned long long*)&t.hval[hslot], (unsigned long long)b.vl[k]);
+            atomicMin((unsigned long long*)claim_val(t, hslot), (unsigned long long)b.vl[k]);
             fresh = b.cur[k] == kEmptyTag;
         } else {
             fresh = claim_cell(t, b.tg[k], b.vl[k], hslot);  // collision: probe onwards
@@ -1236,8 +1236,9 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             u32 s = 0;
             while (i >= pre[s + 1]) ++s;
             h = t.claims[(u64)s * t.claim_cap + (i - pre[s])];
-            const u64 tag = t.htag[h];
-            val = t.hval[h];
+            const ulonglong2 ent = *reinterpret_cast<const ulonglong2*>(claim_tag(t, h));
+            const u64 tag = ent.x;
+            val = ent.y;
             node = (u32)(tag >> 24);
             lin = (u32)tag & 0xFFFFFFu;
         }
@@ -1309,8 +1310,7 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             } else {
                 set_status(t, SIMLOD_OVF_ARENA);
             }
-            t.htag[h] = kEmptyTag;
-            t.hval[h] = ~0ull;
+            *reinterpret_cast<ulonglong2*>(claim_tag(t, h)) = make_ulonglong2(kEmptyTag, ~0ull);
         }
         __syncthreads();
         for (u32 e = tid; e < (1u << kSlotBits); e += kWG) {
@@ -1356,9 +1356,10 @@ __global__ void k_finish(const Member* M, u32 count, u32* status_out) {
 }
 
 // ------------------------------------------------------- reset / export
-__global__ void k_fill_u64(u64* p, u64 n, u64 v) {
+// n pairs (a, b) of u64.
+__global__ void k_fill_pairs(u64* p, u64 n, u64 a, u64 b) {
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
-        p[i] = v;
+        reinterpret_cast<ulonglong2*>(p)[i] = make_ulonglong2(a, b);
 }
 
 __global__ void k_fill_u32(u32* p, u64 n, u32 v) {
@@ -1465,8 +1466,8 @@ hipError_t launch_finish(const Member* m, u32 count, u32* status_out, hipStream_
 }
 hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {
     u32 g = (u32)std::min<u64>((hash_entries + kWG - 1) / kWG, 4096);
-    hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kWG), 0, s, t.htag, hash_entries, kEmptyTag);
-    hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kWG), 0, s, t.hval, hash_entries, ~0ull);
+    hipLaunchKernelGGL(k_fill_pairs, dim3(g), dim3(kWG), 0, s, t.hent, hash_entries, kEmptyTag,
+                       ~0ull);
     const u64 dir_entries = dir_offset(t.dir_depth + 1u);
     const u32 gd = (u32)std::min<u64>((dir_entries + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(k_fill_u32, dim3(gd), dim3(kWG), 0, s, t.dir, dir_entries, kNone);

@@ -118,8 +118,9 @@ struct DevTree {
     u32 hist_cap;
     uint8_t* amask[2];   // per work item: counted in the previous round
     u32 active_cap;
-    u64* htag;           // voxel claim table: (node << 24 | cell) or empty
-    u64* hval;           // (key << 32 | rgba), min-reduced
+    u64* hent;           // voxel claim table, 16-byte entries in one cache line:
+                         // [2h] = (node << 24 | cell) or empty,
+                         // [2h + 1] = (key << 32 | rgba), min-reduced
     u32 hmask;
     u32* claims;         // claim-table slots claimed this pass, kStripes x claim_cap
     u32 claim_cap;
@@ -152,6 +153,11 @@ struct GroupArgs {
     u32 pad;
     Member m[kMaxMembers];
 };
+
+__device__ __forceinline__ u64* claim_tag(const DevTree& t, u32 h) { return t.hent + 2u * (u64)h; }
+__device__ __forceinline__ u64* claim_val(const DevTree& t, u32 h) {
+    return t.hent + 2u * (u64)h + 1u;
+}
 
 __device__ __forceinline__ uint8_t* block_ptr(const DevTree& t, u32 blk) {
     return t.arena + (u64)blk * kBlockBytes;
