@@ -337,6 +337,57 @@ def run_served(args):
     print(json.dumps(result), flush=True)
 
 
+def run_chunk_sweep(args):
+    """Chunk capacity against construction time and memory (the paper's
+    chunk-size experiment, section "Chunks and the Chunk Pool", here on the
+    synthetic aerial workload): the whole 100M-point cloud is inserted in
+    1M-point batches into a fresh octree for each chunk capacity."""
+    import torch
+
+    from paper_2310_03567_amd import simlod
+
+    w = WORKLOADS["aerial"]
+    B = w["batch"]
+    pts = generate("aerial")
+    dev = torch.from_numpy(pts.view(np.uint8).reshape(-1)).to("cuda:0")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    rows = []
+    for C in (500, 1000, 2000, 5000, 10000):
+        cfg = octree_config("aerial")
+        cfg.chunk_capacity = C
+        tree = simlod.Octree(cfg)
+        for rep in range(2):  # the first build warms up, the second is timed
+            tree.reset(stream)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for i in range(len(pts) // B):
+                tree.insert(dev[i * B * 16:(i + 1) * B * 16], stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+        st = tree.stats()
+        tree.close()
+        rec_bytes = (st["num_points"] + st["num_voxels"]) * 20
+        rows.append({"chunk_capacity": C, "construct_ms": round(a.elapsed_time(b), 2),
+                     "chunks": st["chunks_in_use"],
+                     "arena_bytes_used": st["arena_bytes_used"],
+                     "record_bytes": rec_bytes,
+                     "arena_overhead": round(st["arena_bytes_used"] / rec_bytes - 1.0, 4)})
+        log(json.dumps(rows[-1]))
+    best = min(rows, key=lambda r: r["construct_ms"])
+    result = {
+        "metric": "construction time and memory against chunk capacity",
+        "value": best["construct_ms"], "unit": "ms", "n_gpus": 1, "steps": len(pts) // B,
+        "warmup": 1, "ms_per_step": round(best["construct_ms"] / (len(pts) // B), 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "points": len(pts), "batch": B},
+        "sweep": rows,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def cpu_baseline(points, batch, cfg_kw, budget_s=20.0):
     """Sequential C oracle (one thread) on a prefix of the same batches."""
     from oracle import LodConfig
@@ -362,7 +413,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="aerial",
-                    choices=sorted(WORKLOADS) + ["batched", "served"])
+                    choices=sorted(WORKLOADS) + ["batched", "served", "chunk-sweep"])
     ap.add_argument("--offered", default="1.5,6,24",
                     help="served workload: offered loads in G points/s over all streams "
                          "(comma-separated; the last one is reported as value)")
@@ -382,6 +433,9 @@ def main():
         return
     if args.workload == "served":
         run_served(args)
+        return
+    if args.workload == "chunk-sweep":
+        run_chunk_sweep(args)
         return
 
     import torch

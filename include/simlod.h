@@ -250,6 +250,15 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s);
  * is a leaf (the node does not exist yet). */
 int simlod_snapshot_subtree(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s);
 
+/* The same export read the way a renderer consumes the layout: one
+ * workgroup per node starts at the node's first chunk and follows each
+ * chunk's next link (section "Chunks and the Chunk Pool"; the paper's
+ * listing reads a node's chunks this way), instead of the per-node chunk
+ * tables simlod_snapshot_subtree uses.  Identical output; a chunk list that
+ * ends early or continues past the node's last chunk returns HIP with
+ * simlod_last_error naming it. */
+int simlod_snapshot_linked(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s);
+
 /* Counters; synchronizes the handle's last stream.  Works on a poisoned
  * handle (status_bits tells why). */
 int simlod_stats(simlod_octree* h, simlod_stats_data* st);

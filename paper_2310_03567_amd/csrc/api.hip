@@ -566,8 +566,10 @@ int simlod_sync(simlod_octree* h) {
 
 namespace {
 
-// Canonical export of the subtree rooted at the node with `root_path`.
-int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s) {
+// Canonical export of the subtree rooted at the node with `root_path`;
+// linked: read every node through its chunk list instead of its chunk table.
+int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s,
+                   bool linked = false) {
     if (!h || !s) return SIMLOD_ERR_INVALID_ARGUMENT;
     const int nulls = (s->nodes == nullptr) + (s->records == nullptr) + (s->keys == nullptr);
     const bool nodes_only = nulls == 2 && s->nodes != nullptr;
@@ -653,11 +655,15 @@ int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s) 
     u64* d_first = nullptr;
     uint4* d_rec = nullptr;
     u32* d_key = nullptr;
+    u32* d_err = nullptr;
+    u32 walk_err = 0;
     const u64 nrec = std::max<u64>(written, 1);
     bool ok = hipMalloc((void**)&d_nodes, ns * 4ull) == hipSuccess &&
               hipMalloc((void**)&d_first, ns * 8ull) == hipSuccess &&
               hipMalloc((void**)&d_rec, nrec * 16ull) == hipSuccess &&
-              hipMalloc((void**)&d_key, nrec * 4ull) == hipSuccess;
+              hipMalloc((void**)&d_key, nrec * 4ull) == hipSuccess &&
+              hipMalloc((void**)&d_err, sizeof(u32)) == hipSuccess &&
+              hipMemset(d_err, 0, sizeof(u32)) == hipSuccess;
     std::vector<uint4> rec;
     std::vector<u32> key;
     if (ok) {
@@ -665,9 +671,12 @@ int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s) 
         key.resize(written);
         ok = hipMemcpy(d_nodes, order.data(), ns * 4ull, hipMemcpyHostToDevice) == hipSuccess &&
              hipMemcpy(d_first, first.data(), ns * 8ull, hipMemcpyHostToDevice) == hipSuccess &&
-             launch_gather(h->t, d_nodes, d_first, ns, d_rec, d_key, nullptr) == hipSuccess &&
+             (linked ? launch_walk(h->t, d_nodes, d_first, ns, d_rec, d_key, d_err, nullptr)
+                     : launch_gather(h->t, d_nodes, d_first, ns, d_rec, d_key, nullptr)) ==
+                 hipSuccess &&
              hipMemcpy(rec.data(), d_rec, written * 16ull, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(key.data(), d_key, written * 4ull, hipMemcpyDeviceToHost) == hipSuccess;
+             hipMemcpy(key.data(), d_key, written * 4ull, hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(&walk_err, d_err, sizeof(u32), hipMemcpyDeviceToHost) == hipSuccess;
     }
     const hipError_t ge = ok ? hipSuccess : hipGetLastError();
     if (!ok) note_error("snapshot gather", ge);
@@ -676,7 +685,12 @@ int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s) 
     (void)hipFree(d_first);
     (void)hipFree(d_rec);
     (void)hipFree(d_key);
+    (void)hipFree(d_err);
     if (!ok) return oom ? SIMLOD_ERR_OUT_OF_MEMORY : SIMLOD_ERR_HIP;
+    if (walk_err) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "chunk list inconsistent (%u)", walk_err);
+        return SIMLOD_ERR_HIP;
+    }
     fill_nodes();
     // Canonical order inside a node: by key.  Nodes are independent; large
     // exports sort them on several host threads.
@@ -732,6 +746,10 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s) {
 
 int simlod_snapshot_subtree(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s) {
     return export_subtree(h, path, s);
+}
+
+int simlod_snapshot_linked(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s) {
+    return export_subtree(h, path, s, true);
 }
 
 int simlod_stats(simlod_octree* h, simlod_stats_data* st) {

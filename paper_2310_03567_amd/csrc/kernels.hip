@@ -1405,6 +1405,35 @@ __global__ __launch_bounds__(256) void k_gather(DevTree t, const u32* nodes, con
     }
 }
 
+// The same copy through the chunk lists, the layout's reader: one
+// workgroup per node starts at the node's first chunk and follows each
+// chunk's next link, copying a chunk's records together (section "Chunks
+// and the Chunk Pool").  A list that ends early or runs past the node's
+// last chunk sets *err.
+__global__ __launch_bounds__(256) void k_walk(DevTree t, const u32* nodes, const u64* first,
+                                              u32 nn, uint4* out_rec, u32* out_key, u32* err) {
+    for (u32 i = blockIdx.x; i < nn; i += gridDim.x) {
+        const u32 node = nodes[i];
+        const u32 cnt = t.count[node];
+        if (cnt == 0u) continue;
+        const u64 f = first[i];
+        u32 chunk = table_of(t, node)[0];
+        for (u32 base = 0; base < cnt; base += t.C) {
+            if (chunk == kNone || (u64)chunk + t.chunk_blocks > (u64)t.arena_blocks) {
+                if (threadIdx.x == 0) atomicOr(err, 1u);
+                break;
+            }
+            const u32 m = min(t.C, cnt - base);
+            for (u32 s = threadIdx.x; s < m; s += kWG) {
+                out_rec[f + base + s] = chunk_recs(t, chunk)[s];
+                out_key[f + base + s] = chunk_keys(t, chunk)[s];
+            }
+            chunk = *chunk_next(t, chunk);
+        }
+        if (chunk != kNone && threadIdx.x == 0) atomicOr(err, 2u);  // list continues
+    }
+}
+
 // ------------------------------------------------------- host launchers
 static inline u32 grid_for(u64 items, u32 lo, u32 hi) {
     u64 g = (items + kWG - 1) / kWG;
@@ -1472,6 +1501,12 @@ hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {
     const u32 gd = (u32)std::min<u64>((dir_entries + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(k_fill_u32, dim3(gd), dim3(kWG), 0, s, t.dir, dir_entries, kNone);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_walk(const DevTree& t, const u32* nodes, const u64* first, u32 nn,
+                       uint4* out_rec, u32* out_key, u32* err, hipStream_t s) {
+    const u32 g = std::max<u32>(1u, std::min<u32>(nn, 4096u));
+    hipLaunchKernelGGL(k_walk, dim3(g), dim3(kWG), 0, s, t, nodes, first, nn, out_rec, out_key, err);
     return hipGetLastError();
 }
 hipError_t launch_gather(const DevTree& t, const u32* nodes, const u64* first, u32 nn,

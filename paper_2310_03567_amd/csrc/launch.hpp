@@ -32,6 +32,8 @@ hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const Laun
                                hipStream_t s);
 hipError_t launch_finish(const Member* m, u32 count, u32* status_out, hipStream_t s);
 hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s);
+hipError_t launch_walk(const DevTree& t, const u32* nodes, const u64* first, u32 nn,
+                       uint4* out_rec, u32* out_key, u32* err, hipStream_t s);
 hipError_t launch_gather(const DevTree& t, const u32* nodes, const u64* first, u32 nn,
                          uint4* out_rec, u32* out_key, hipStream_t s);
 

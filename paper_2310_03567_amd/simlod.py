@@ -103,6 +103,8 @@ EXPORTS = {
     "simlod_snapshot": ([ctypes.c_void_p, ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_snapshot_subtree": ([ctypes.c_void_p, ctypes.c_uint64,
                                  ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
+    "simlod_snapshot_linked": ([ctypes.c_void_p, ctypes.c_uint64,
+                                ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_stats": ([ctypes.c_void_p, ctypes.POINTER(StatsData)], ctypes.c_int),
     "simlod_sync": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -253,11 +255,16 @@ def insert_batch(handle: int, points, stream=None) -> None:
     del keep
 
 
-def snapshot(handle: int, path: int | None = None, nodes_only: bool = False):
+def snapshot(handle: int, path: int | None = None, nodes_only: bool = False,
+             linked: bool = False):
     """Canonical export: (nodes NODE_DTYPE, records POINT_DTYPE, keys uint32)
     of the whole octree, or of the subtree of the node with ``path``; with
-    ``nodes_only`` the records and keys come back empty."""
-    if path is None:
+    ``nodes_only`` the records and keys come back empty; ``linked`` reads
+    the records through the chunk lists."""
+    if linked:
+        p = 1 if path is None else path
+        call, name = (lambda b: lib.simlod_snapshot_linked(handle, p, b)), "simlod_snapshot_linked"
+    elif path is None:
         call, name = (lambda b: lib.simlod_snapshot(handle, b)), "simlod_snapshot"
     else:
         call, name = (lambda b: lib.simlod_snapshot_subtree(handle, path, b)), "simlod_snapshot_subtree"
@@ -325,8 +332,9 @@ class Octree:
     def insert(self, points, stream=None) -> None:
         insert_batch(self.handle, points, stream)
 
-    def snapshot(self, path: int | None = None, nodes_only: bool = False) -> Snapshot:
-        return Snapshot(*snapshot(self.handle, path, nodes_only))
+    def snapshot(self, path: int | None = None, nodes_only: bool = False,
+                 linked: bool = False) -> Snapshot:
+        return Snapshot(*snapshot(self.handle, path, nodes_only, linked))
 
     def stats(self) -> dict:
         return stats(self.handle)

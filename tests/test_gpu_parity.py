@@ -233,3 +233,23 @@ def canonical_of(s):
     from oracle.canonical import CanonicalTree
 
     return CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys)
+
+
+@pytest.mark.parametrize("C", [1, 3, 64, 1000])
+def test_chunk_list_reader_equals_table_export(C):
+    """Reading every node through its linked chunk list (the renderer's
+    access pattern) gives exactly the canonical export, after splits that
+    returned chunks to the pool and reused them."""
+    import pointgen
+
+    p = pointgen.tiny_planes(120_000, seed=17)
+    cfg = LodConfig(leaf_capacity=1_500, grid_bits=5, max_depth=9, chunk_capacity=C)
+    log(f"case: chunk lists C={C}")
+    with make_octree(cfg, arena_bytes=1 << 30) as tree:
+        insert_batches(tree, to_device(p), [5_000, 40_000, 75_000])
+        a = tree.snapshot()
+        b = tree.snapshot(linked=True)
+    assert a.nodes.tobytes() == b.nodes.tobytes()
+    assert a.records.tobytes() == b.records.tobytes()
+    assert np.array_equal(a.keys, b.keys)
+    assert_trees_equal(canonical_of(b), O1.build(p, cfg))
