@@ -231,12 +231,15 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
                          [&] { return launch_count_leaves(ga, items, sh, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(M, cnt, items, s); });
-    for (u32 k = 2; k <= rounds && e == hipSuccess; ++k) {
+    if (rounds >= 2u && e == hipSuccess) {
         e = timed(tm, SIMLOD_KERNEL_COUNT_HIST, s,
-                  [&] { return launch_count_hist(M, cnt, items, k, sh, s); });
+                  [&] { return launch_count_hist(M, cnt, items, 2u, sh, s); });
         if (e == hipSuccess)
-            e = timed(tm, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(M, cnt, k, s); });
+            e = timed(tm, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(M, cnt, 2u, s); });
     }
+    if (rounds >= 3u && e == hipSuccess)  // the rare later rounds: one launch
+        e = timed(tm, SIMLOD_KERNEL_BUILD, s,
+                  [&] { return launch_rounds_tail(M, cnt, 3u, rounds, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(M, cnt, 0u, s); });
     if (e == hipSuccess)
@@ -406,7 +409,7 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
               dalloc(h, &t.amask[1], work) && dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
-              dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 1);
+              dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 2);  // + pass barrier words
     const u32 C = cfg->chunk_capacity;
     const u64 chunk_bytes = (u64)C * 20u + 4u;
     t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);
@@ -1048,7 +1051,8 @@ int simlod_group_create(simlod_octree* const* members, uint32_t count, uint32_t 
         g->rounds = std::max(g->rounds, expansion_rounds(h->cfg.max_depth));
         g->cap_items += h->cfg.max_batch;
     }
-    bool ok = hipMalloc((void**)&g->d_table, count * sizeof(Member)) == hipSuccess &&
+    // one entry more: the pass barrier's two words follow the members
+    bool ok = hipMalloc((void**)&g->d_table, (count + 1u) * sizeof(Member)) == hipSuccess &&
               hipMalloc((void**)&g->d_status, count * sizeof(u32)) == hipSuccess &&
               hipHostMalloc((void**)&g->h_status, count * sizeof(u32), hipHostMallocDefault) ==
                   hipSuccess &&
@@ -1491,7 +1495,7 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
     sv->cfg = *cfg;
     sv->slots.resize(cfg->max_streams);
     bool ok = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) == hipSuccess &&
-              hipMalloc((void**)&sv->d_table, kMaxMembers * sizeof(Member)) == hipSuccess &&
+              hipMalloc((void**)&sv->d_table, (kMaxMembers + 1u) * sizeof(Member)) == hipSuccess &&
               hipMalloc((void**)&sv->d_status, kMaxMembers * sizeof(u32)) == hipSuccess &&
               hipHostMalloc((void**)&sv->h_status, kStatusRing * kMaxMembers * sizeof(u32),
                             hipHostMallocDefault) == hipSuccess;

@@ -252,6 +252,12 @@ __device__ __forceinline__ u32 next_tile(u32 tile, u32 ntiles) {
     return nx < ntiles ? nx : kNone;
 }
 
+// Two words after the pass's member table: arrivals and generation of the
+// tail kernel's grid barrier (zeroed by the pass's first kernel).
+__device__ __forceinline__ u32* pass_barrier(const Member* M, u32 count) {
+    return reinterpret_cast<u32*>(const_cast<Member*>(M) + count);
+}
+
 // Reads a member of the group table into registers.
 __device__ __forceinline__ DevTree tree_of(const Member* M, u32 c) { return *M[c].tree; }
 
@@ -269,6 +275,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     const u32 count = ga.count;
     const Member* M = ga.m;
     if (blockIdx.x == 0 && tid < count) ga.table[tid] = M[tid];
+    if (blockIdx.x == 0 && tid < 2u) pass_barrier(ga.table, count)[tid] = 0u;
     for (u32 i = tid; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
@@ -400,7 +407,7 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // root's histogram at each of the kHistLevels levels below it (levels beyond
 // Dmax do not exist).  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
-__global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round) {
+__device__ void count_hist_body(const Member* M, u32 count, u32 round) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
@@ -517,7 +524,7 @@ __device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
 // descendants receive 8 consecutive children each (one node-count atomic per
 // root, in level order), occupancy grids (cleared later, in k_alloc) and
 // directory entries.
-__global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 round) {
+__device__ void build_body(const Member* M, u32 count, u32 round) {
     __shared__ u32 s_h[kHistEntries];   // the root's histogram
     __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
     __shared__ u32 s_sp[kSplitSlots];   // split index of inner nodes
@@ -673,6 +680,84 @@ __global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 r
             t.final_list[fb + s_q[i]] = make_uint2(nd, s_h[hist_level_offset(lv) + rel]);
         }
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round) {
+    count_hist_body(M, count, round);
+}
+
+__global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 round) {
+    build_body(M, count, round);
+}
+
+constexpr u32 kBarrierSpin = 1u << 20;  // polls before a barrier gives up (~1 s)
+
+// Grid-wide barrier of a kernel whose workgroups are all resident: every
+// workgroup releases its writes, counts itself in and waits for the
+// generation to move on.  The wait is bounded, so a grid that cannot
+// complete the barrier still exits (returns false).
+__device__ bool grid_barrier(u32* bar) {
+    __shared__ u32 s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const u32 gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        u32 ok = 1u;
+        if (atomicAdd(&bar[0], 1u) == gridDim.x - 1u) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            u32 spin = 0u;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (++spin == kBarrierSpin) {
+                    ok = 0u;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0u;
+}
+
+// Expansion rounds first..last in one launch.  After the second round a
+// pass rarely has pending roots left (only where one pass splits a region
+// more than kHistLevels levels deep), so the kernel usually finds none and
+// exits at once, instead of six launches that each find nothing.  When
+// there are, the rounds run here, separated by grid barriers: the grid
+// (kTailWGs workgroups, at most two per CU by LDS) is all resident.  A
+// barrier that times out poisons every member of the pass.
+constexpr u32 kTailWGs = 256;
+
+__global__ __launch_bounds__(256) void k_rounds_tail(const Member* M, u32 count, u32 first,
+                                                     u32 last) {
+    __shared__ u32 s_any;
+    u32* bar = pass_barrier(M, count);
+    for (u32 round = first; round <= last; ++round) {
+        // pending roots from the round before: the same for every workgroup
+        // (written before the last barrier or launch, read after it)
+        if (threadIdx.x == 0) {
+            u32 any = 0u;
+            for (u32 c = 0; c < count && !any; ++c)
+                any = M[c].tree->ctr->pending_count[(round - 1u) & 1u] != 0u;
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) return;
+        count_hist_body(M, count, round);
+        bool ok = grid_barrier(bar);
+        if (ok) {
+            build_body(M, count, round);
+            ok = grid_barrier(bar);
+        }
+        if (!ok) {
+            if (threadIdx.x < count) atomicOr(&M[threadIdx.x].tree->ctr->status, SIMLOD_OVF_INTERNAL);
+            return;
+        }
     }
 }
 
@@ -1471,6 +1556,10 @@ hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
 }
 hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
     hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, m, count, round);
+    return hipGetLastError();
+}
+hipError_t launch_rounds_tail(const Member* m, u32 count, u32 first, u32 last, hipStream_t s) {
+    hipLaunchKernelGGL(k_rounds_tail, dim3(kTailWGs), dim3(kWG), 0, s, m, count, first, last);
     return hipGetLastError();
 }
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
