@@ -113,6 +113,29 @@ u64 next_pow2(u64 v) {
     return p;
 }
 
+u32 bit_length(u64 v) {
+    u32 b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+// Bits of a cell identity node << 3r | cell.
+u32 tag_bits_for(const simlod_config* c) {
+    return bit_length((u64)c->max_nodes - 1u) + 3u * c->grid_bits;
+}
+
+// Claim-table entries: twice the backlog, and enough that a cell identity's
+// bits beyond the table index fit the claim word's tag (kRemBits).
+u64 hash_entries_for(const simlod_config* c) {
+    u64 e = next_pow2(2 * c->backlog_capacity);
+    const u32 tb = tag_bits_for(c);
+    if (tb > kRemBits) e = std::max<u64>(e, 1ull << (tb - kRemBits));
+    return e;
+}
+
 bool cfg_valid(const simlod_config* c) {
     if (c->grid_bits > 8 || c->max_depth > 21 || c->grid_bits + c->max_depth > 24) return false;
     if (c->max_depth + 1 > (u32)kMaxRounds) return false;
@@ -333,13 +356,15 @@ int sync_handle(simlod_octree* h) {
 static void configure_tree(simlod_octree* h, const simlod_config* cfg, u64 arena_bytes) {
     DevTree& t = h->t;
     h->cfg = *cfg;
-    h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
+    h->hash_entries = hash_entries_for(cfg);
     t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
     t.max_nodes = cfg->max_nodes;
     t.hist_cap = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
     t.spill_cap = (u32)cfg->spill_capacity;
     t.active_cap = (u32)(cfg->max_batch + cfg->spill_capacity);
     t.hmask = (u32)(h->hash_entries - 1);
+    t.hash_bits = bit_length(h->hash_entries) - 1u;
+    t.tag_bits = tag_bits_for(cfg);
     t.claim_cap = (u32)cfg->backlog_capacity;
     const u64 chunk_bytes = (u64)cfg->chunk_capacity * 20u + 4u;
     t.chunk_blocks = (u32)((chunk_bytes + kBlockBytes - 1) / kBlockBytes);
@@ -375,7 +400,7 @@ static Footprint footprint_of(const simlod_config* c) {
     f.v[2] = c->spill_capacity;
     f.v[3] = c->hist_capacity ? c->hist_capacity : 8192u;
     f.v[4] = c->max_batch + c->spill_capacity;
-    f.v[5] = next_pow2(2 * c->backlog_capacity);
+    f.v[5] = hash_entries_for(c);
     f.v[6] = c->backlog_capacity * kStripes;
     f.v[7] = arena_blocks;
     f.v[8] = arena_blocks / chunk_blocks + 1;
@@ -393,7 +418,7 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
     std::memset(&t, 0, sizeof(t));
     const u64 N = cfg->max_nodes;
     const u64 work = cfg->max_batch + cfg->spill_capacity;
-    h->hash_entries = next_pow2(2 * cfg->backlog_capacity);
+    h->hash_entries = hash_entries_for(cfg);
     t.dir_depth = std::min<u32>(cfg->max_depth, kDirMaxDepth);
     const u32 hist_slots = cfg->hist_capacity ? cfg->hist_capacity : 8192u;
     bool ok = dalloc(h, &t.child, N) && dalloc(h, &t.count, N) && dalloc(h, &t.cnt, N) &&

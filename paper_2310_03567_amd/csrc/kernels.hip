@@ -47,7 +47,6 @@ constexpr u32 kWG = 256;  // 4 wavefronts; the LDS tables and scans assume it
 static_assert(kWG == 256, "workgroup scans and LDS tables are laid out for 4 wavefronts");
 constexpr u32 kLdsBits = 11;
 constexpr u32 kLds = 1u << kLdsBits;
-constexpr u32 kMaxProbe = 4096;
 constexpr u32 kHistKey = 0x80000000u;  // LDS key flag: a histogram counter
 
 // Renumbers workgroups so that each of the 8 XCDs (which receive workgroups
@@ -881,24 +880,47 @@ __global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 v
 }
 
 // ------------------------------------------------------- voxel claim table
-// Inserts (node, cell) and min-reduces (key << 32 | rgba) into its value.
-// Returns true for the call that created the entry.
-__device__ __forceinline__ bool claim_cell(const DevTree& t, u64 tag, u64 val, u32& slot) {
-    u32 h = (u32)mix64(tag) & t.hmask;
-    for (u32 p = 0; p < kMaxProbe; ++p) {
-        u64 cur = *claim_tag(t, h);
-        if (cur == kEmptyTag)
-            cur = atomicCAS((unsigned long long*)claim_tag(t, h), (unsigned long long)kEmptyTag,
-                            (unsigned long long)tag);
-        if (cur == kEmptyTag || cur == tag) {
-            atomicMin((unsigned long long*)claim_val(t, h), (unsigned long long)val);
+// Identity of a cell in the claim table: node << 3r | cell.
+__device__ __forceinline__ u64 cell_identity(const DevTree& t, u64 ltag) {
+    return ((ltag >> 24) << (3u * t.r)) | (ltag & 0xFFFFFFull);
+}
+
+// Claims cell T (home entry, remainder) for `key`, probing from distance d0
+// on: an empty entry takes the claim word, an entry holding the cell keeps
+// the smaller key (atomic min only when ours is smaller).  Returns false if
+// no entry was found (status set); fresh = this call created the entry.
+__device__ __forceinline__ bool claim_probe(const DevTree& t, u32 home, u32 rem, u32 key, u32 d0,
+                                            u32& slot, bool& fresh) {
+    for (u32 d = d0; d < (1u << kDistBits); ++d) {
+        const u32 h = (home + d) & t.hmask;
+        const u32 tg = (rem << kDistBits) | d;
+        const u64 mine = ((u64)tg << 32) | key;
+        u64* w = claim_word_at(t, h);
+        u64 cur = *w;
+        if (cur == kEmptyWord)
+            cur = atomicCAS((unsigned long long*)w, (unsigned long long)kEmptyWord,
+                            (unsigned long long)mine);
+        if (cur == kEmptyWord) {
             slot = h;
-            return cur == kEmptyTag;
+            fresh = true;
+            return true;
         }
-        h = (h + 1u) & t.hmask;
+        if ((u32)(cur >> 32) == tg) {
+            if ((u32)cur > key) atomicMin((unsigned long long*)w, (unsigned long long)mine);
+            slot = h;
+            fresh = false;
+            return true;
+        }
     }
     set_status(t, SIMLOD_OVF_HASH);
     return false;
+}
+
+// A claim by a spilled point (key below the batch's first key) also
+// min-reduces (key << 32 | rgba) in the entry's side word: spilled records
+// cannot be found from their keys, batch records can (batch[key - base]).
+__device__ __forceinline__ void claim_spill_colour(const DevTree& t, u32 slot, u64 val) {
+    atomicMin((unsigned long long*)claim_spill_at(t, slot), (unsigned long long)val);
 }
 
 // ------------------------------------------------------- sample and store
@@ -979,9 +1001,9 @@ __device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 v
 __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
                                                  u32 rgba, bool batch_item, u32 lane, u64* ctag,
-                                                 u64* cval, u32 stripe, u32* s_claims,
-                                                 u32* s_nclaims, u32* s_vkey, u32* s_vcnt,
-                                                 u32* s_vfill) {
+                                                 u64* cval, u32 stripe, u32 base_key,
+                                                 u32* s_claims, u32* s_nclaims, u32* s_vkey,
+                                                 u32* s_vcnt, u32* s_vfill) {
     u64 tag = kEmptyTag;
     if (inner) {
         const u32 lin = cell_lin(qx, qy, qz, t.Dmax - d, t.r, t.R - 1u);
@@ -993,20 +1015,27 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
     if (cand && !cand_insert(ctag, cval, tag, val, batch_item)) {  // no entry: claim now
-        u32 hslot;
-        if (claim_cell(t, tag, val, hslot))
-            stage_claim(t, hslot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt, s_vfill);
+        u32 home, rem, slot;
+        bool fresh;
+        claim_home(t, cell_identity(t, tag), home, rem);
+        if (claim_probe(t, home, rem, key, 0u, slot, fresh)) {
+            if (key < base_key) claim_spill_colour(t, slot, val);
+            if (fresh)
+                stage_claim(t, slot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt, s_vfill);
+        }
     }
 }
 
 // Claims of one tile, in two halves so that other global atomics can share
 // the round trip: claim_issue takes a thread's entries of the LDS candidate
-// table (clearing them) and issues their claim-table CASes; claim_resolve
-// min-reduces the values and stages the claims this workgroup created.
+// table and issues a CAS of each one's claim word into its home entry;
+// claim_resolve handles what the CAS found (an entry created, the cell's
+// entry holding a larger key, another cell's entry: probe on) and stages the
+// claims this workgroup created.
 constexpr u32 kCandPer = kCands / 256u;
 struct ClaimBatch {
     u64 tg[kCandPer], vl[kCandPer], cur[kCandPer];
-    u32 hh[kCandPer];
+    u32 hh[kCandPer], rm[kCandPer];
 };
 
 // keep: the workgroup's next tile belongs to the same octree, so submitted
@@ -1024,32 +1053,41 @@ __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cv
             ctag[i] = live && keep ? (tg | kSubmitted) : kEmptyTag;
             cval[i] = ~0ull;
         }
-        b.hh[k] = (u32)mix64(b.tg[k]) & t.hmask;
+        claim_home(t, cell_identity(t, b.tg[k]), b.hh[k], b.rm[k]);
     }
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k)
         b.cur[k] = b.tg[k] != kEmptyTag
-                       ? atomicCAS((unsigned long long*)claim_tag(t, b.hh[k]),
-                                   (unsigned long long)kEmptyTag, (unsigned long long)b.tg[k])
+                       ? atomicCAS((unsigned long long*)claim_word_at(t, b.hh[k]),
+                                   (unsigned long long)kEmptyWord,
+                                   (unsigned long long)(((u64)(b.rm[k] << kDistBits) << 32) |
+                                                        (b.vl[k] >> 32)))
                        : 0ull;
 }
 
 __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch& b, u32 stripe,
-                                              u32* s_claims, u32* s_nclaims, u32* s_vkey,
-                                              u32* s_vcnt, u32* s_vfill) {
+                                              u32 base_key, u32* s_claims, u32* s_nclaims,
+                                              u32* s_vkey, u32* s_vcnt, u32* s_vfill) {
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k) {
         if (b.tg[k] == kEmptyTag) continue;
-        bool fresh;
-        u32 hslot = b.hh[k];
-        if (b.cur[k] == kEmptyTag || b.cur[k] == b.tg[k]) {
-            atomicMin((unsigned long long*)claim_val(t, hslot), (unsigned long long)b.vl[k]);
-            fresh = b.cur[k] == kEmptyTag;
-        } else {
-            fresh = claim_cell(t, b.tg[k], b.vl[k], hslot);  // collision: probe onwards
+        const u32 key = (u32)(b.vl[k] >> 32);
+        const u32 tg0 = b.rm[k] << kDistBits;
+        bool fresh = false, found = true;
+        u32 slot = b.hh[k];
+        if (b.cur[k] == kEmptyWord) {
+            fresh = true;
+        } else if ((u32)(b.cur[k] >> 32) == tg0) {
+            if ((u32)b.cur[k] > key)
+                atomicMin((unsigned long long*)claim_word_at(t, slot),
+                          (unsigned long long)(((u64)tg0 << 32) | key));
+        } else {  // another cell's entry: probe on
+            found = claim_probe(t, b.hh[k], b.rm[k], key, 1u, slot, fresh);
         }
+        if (!found) continue;
+        if (key < base_key) claim_spill_colour(t, slot, b.vl[k]);
         if (fresh)
-            stage_claim(t, hslot, (u32)(b.tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey,
+            stage_claim(t, slot, (u32)(b.tg[k] >> 24), stripe, s_claims, s_nclaims, s_vkey,
                         s_vcnt, s_vfill);
     }
 }
@@ -1155,6 +1193,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         const u32 c = member_of(s_pre, count, tile);
         const DevTree t = tree_of(M, c);
         const u32 S = t.ctr->spill_count;
+        const u32 base_key = M[c].base_key;
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         const bool valid = j < S + M[c].n;
         const bool batch_item = j >= S;
@@ -1195,8 +1234,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
                 desc = false;
             }
             level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w,
-                             batch_item, lane, s_ctag, s_cval, stripe, s_claims, &s_nclaims,
-                             s_vkey, s_vcnt, &s_vfill);
+                             batch_item, lane, s_ctag, s_cval, stripe, base_key, s_claims,
+                             &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
@@ -1212,8 +1251,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
             level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, batch_item, lane,
-                             s_ctag, s_cval, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt,
-                             &s_vfill);
+                             s_ctag, s_cval, stripe, base_key, s_claims, &s_nclaims, s_vkey,
+                             s_vcnt, &s_vfill);
             if (inner) node = ch + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
@@ -1245,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
             s_lcnt[i] = 0u;
         }
         if (nx != kNone) fetch(cn, nx, rec_n, key_n);
-        claim_resolve(t, cb, stripe, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
+        claim_resolve(t, cb, stripe, base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         __syncthreads();
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
@@ -1321,11 +1360,15 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             u32 s = 0;
             while (i >= pre[s + 1]) ++s;
             h = t.claims[(u64)s * t.claim_cap + (i - pre[s])];
-            const ulonglong2 ent = *reinterpret_cast<const ulonglong2*>(claim_tag(t, h));
-            const u64 tag = ent.x;
-            val = ent.y;
-            node = (u32)(tag >> 24);
-            lin = (u32)tag & 0xFFFFFFu;
+            const ulonglong2 ent = *reinterpret_cast<const ulonglong2*>(claim_word_at(t, h));
+            const u64 T = claim_identity(t, h, (u32)(ent.x >> 32));
+            const u32 key = (u32)ent.x;
+            node = (u32)(T >> (3u * t.r));
+            lin = (u32)(T & low_bits(3u * t.r));
+            // the winner's colour: from the batch record, or (a spilled
+            // point) from the side word
+            const u32 rgba = key >= M[c].base_key ? M[c].batch[key - M[c].base_key].w : (u32)ent.y;
+            val = ((u64)key << 32) | rgba;
         }
         // slot reservation: LDS histogram per node, one global atomic per node
         const Run r = lane_runs(node);
@@ -1395,7 +1438,7 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             } else {
                 set_status(t, SIMLOD_OVF_ARENA);
             }
-            *reinterpret_cast<ulonglong2*>(claim_tag(t, h)) = make_ulonglong2(kEmptyTag, ~0ull);
+            *reinterpret_cast<ulonglong2*>(claim_word_at(t, h)) = make_ulonglong2(kEmptyWord, ~0ull);
         }
         __syncthreads();
         for (u32 e = tid; e < (1u << kSlotBits); e += kWG) {

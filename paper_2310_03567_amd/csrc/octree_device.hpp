@@ -118,10 +118,13 @@ struct DevTree {
     u32 hist_cap;
     uint8_t* amask[2];   // per work item: counted in the previous round
     u32 active_cap;
-    u64* hent;           // voxel claim table, 16-byte entries in one cache line:
-                         // [2h] = (node << 24 | cell) or empty,
-                         // [2h + 1] = (key << 32 | rgba), min-reduced
+    u64* hent;           // voxel claim table, 16-byte entries (one cache line):
+                         // [2h] = claim word (tag << 32 | key), min-reduced,
+                         // [2h + 1] = (key << 32 | rgba) of spilled claimants,
+                         // min-reduced (see claim_home)
     u32 hmask;
+    u32 hash_bits;       // log2 of the claim table's entries
+    u32 tag_bits;        // bits of a cell's identity node << 3r | cell
     u32* claims;         // claim-table slots claimed this pass, kStripes x claim_cap
     u32 claim_cap;
     // geometry and parameters
@@ -154,9 +157,61 @@ struct GroupArgs {
     Member m[kMaxMembers];
 };
 
-__device__ __forceinline__ u64* claim_tag(const DevTree& t, u32 h) { return t.hent + 2u * (u64)h; }
-__device__ __forceinline__ u64* claim_val(const DevTree& t, u32 h) {
+__device__ __forceinline__ u64* claim_word_at(const DevTree& t, u32 h) {
+    return t.hent + 2u * (u64)h;
+}
+__device__ __forceinline__ u64* claim_spill_at(const DevTree& t, u32 h) {
     return t.hent + 2u * (u64)h + 1u;
+}
+
+// Claim table addressing.  A cell's identity T = node << 3r | cell has
+// tag_bits bits.  An invertible mix of those bits (multiply by an odd
+// constant mod 2^n, xor-shift by at least n/2, multiply again) gives the
+// home entry (its top hash_bits bits) and a remainder (the other bits, at
+// most kRemBits); an entry then holds (remainder << kDistBits | probe
+// distance) as its 32-bit tag, which together with the entry's index
+// determines T.  So one 64-bit word (tag << 32 | key) carries both the
+// cell and the smallest key claimed for it, and a claim is one atomic.
+constexpr u32 kDistBits = 7;  // linear probing up to 127 entries past home
+constexpr u32 kRemBits = 24;  // the tag stays below 2^31, never the empty word's
+constexpr u64 kMixA = 0x9E3779B97F4A7C15ull;
+constexpr u64 kMixAinv = 0xF1DE83E19937733Dull;  // kMixA * kMixAinv = 1 mod 2^64
+constexpr u64 kEmptyWord = ~0ull;
+
+__device__ __forceinline__ u64 low_bits(u32 n) { return n >= 64u ? ~0ull : (1ull << n) - 1ull; }
+
+__device__ __forceinline__ u64 tag_mix(u64 x, u32 n) {
+    const u64 m = low_bits(n);
+    x = (x * kMixA) & m;
+    x ^= x >> ((n + 1u) / 2u);
+    return (x * kMixA) & m;
+}
+
+__device__ __forceinline__ u64 tag_unmix(u64 x, u32 n) {
+    const u64 m = low_bits(n);
+    x = (x * kMixAinv) & m;
+    x ^= x >> ((n + 1u) / 2u);  // an involution when the shift is >= n/2
+    return (x * kMixAinv) & m;
+}
+
+__device__ __forceinline__ u32 rem_bits_of(const DevTree& t) {
+    return t.tag_bits > t.hash_bits ? t.tag_bits - t.hash_bits : 0u;
+}
+
+// Home entry and remainder of identity T.
+__device__ __forceinline__ void claim_home(const DevTree& t, u64 T, u32& home, u32& rem) {
+    const u64 m = tag_mix(T, t.tag_bits);
+    const u32 rb = rem_bits_of(t);
+    home = (u32)(m >> rb) & t.hmask;
+    rem = (u32)(m & low_bits(rb));
+}
+
+// Identity T of the cell whose claim word at entry h carries tag tg.
+__device__ __forceinline__ u64 claim_identity(const DevTree& t, u32 h, u32 tg) {
+    const u32 d = tg & ((1u << kDistBits) - 1u);
+    const u64 home = (u64)((h - d) & t.hmask);
+    const u32 rb = rem_bits_of(t);
+    return tag_unmix((home << rb) | (u64)(tg >> kDistBits), t.tag_bits);
 }
 
 __device__ __forceinline__ uint8_t* block_ptr(const DevTree& t, u32 blk) {
