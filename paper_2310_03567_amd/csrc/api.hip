@@ -61,6 +61,9 @@ struct simlod_octree {
 
 namespace {
 
+// Events that only order streams of one device need no system-scope fence.
+constexpr unsigned kOrderingEvent = hipEventDisableTiming | hipEventDisableSystemFence;
+
 thread_local char g_last_error[512] = "";
 
 void note_error(const char* what, hipError_t e) {
@@ -103,7 +106,7 @@ bool dalloc(simlod_octree* h, T** p, u64 count) {
         return false;
     }
     h->dev_allocs.push_back(v);
-    *p = static_cast<T*>(v);
+    *p = (T*)v;  // a C-style cast: T may carry the device address space
     return true;
 }
 
@@ -200,8 +203,11 @@ hipEvent_t take_event(Timing& tm) {
         tm.free_events.pop_back();
         return e;
     }
+    // Timing only: without the system-scope fence an event costs no L2
+    // writeback and invalidation (several microseconds of idle GPU, and a
+    // cold L2 for the next kernel).
     hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
 }
 
@@ -284,13 +290,17 @@ hipError_t enqueue_pass(simlod_octree* h, const uint4* batch, u32 n, u32 base_ke
     GroupArgs ga{};
     ga.table = h->d_members;
     ga.count = 1;
-    ga.m[0] = Member{h->d_tree, batch, n, base_key};
+    ga.m[0] = make_member(h->d_tree, batch, n, base_key);
     hipError_t e = enqueue_group_pass(ga, n, expansion_rounds(h->cfg.max_depth), h->shape, &h->tm,
                                       nullptr, s);
-    if (e == hipSuccess)
+    // At most one status copy in flight: the status word is sticky, so a
+    // later copy reports every earlier error, and a copy with its event
+    // (a system-scope fence) per pass would cost more than a short kernel.
+    if (e == hipSuccess && !h->status_pending) {
         e = hipMemcpyAsync(h->h_status, &h->t.ctr->status, sizeof(u32), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(h->status_ev, s);
-    if (e == hipSuccess) h->status_pending = true;
+        if (e == hipSuccess) e = hipEventRecord(h->status_ev, s);
+        if (e == hipSuccess) h->status_pending = true;
+    }
     return e;
 }
 
@@ -432,7 +442,8 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.zero_list, N) &&
               dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
-              dalloc(h, &t.amask[1], work) && dalloc(h, &t.hent, 2 * h->hash_entries) &&
+              dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, work) &&
+              dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
               dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 2);  // + pass barrier words
     const u32 C = cfg->chunk_capacity;
@@ -926,17 +937,8 @@ void group_free(simlod_group* g) {
     free_timing(g->tune_tm);
 }
 
-// Marks members whose status word came back non-zero as poisoned.
-int group_poll(simlod_group* g, bool wait) {
-    if (!g->status_pending) return SIMLOD_OK;
-    const hipError_t e = wait ? hipEventSynchronize(g->status_ev) : hipEventQuery(g->status_ev);
-    if (e == hipErrorNotReady) return SIMLOD_OK;
-    g->status_pending = false;
-    if (e != hipSuccess) {
-        note_error("group status event", e);
-        clear_stale_error();
-        return SIMLOD_ERR_HIP;
-    }
+// Marks members whose status word in h_status is non-zero as poisoned.
+int group_apply_status(simlod_group* g) {
     int rc = SIMLOD_OK;
     for (size_t i = 0; i < g->members.size(); ++i) {
         simlod_octree* h = g->members[i];
@@ -949,17 +951,28 @@ int group_poll(simlod_group* g, bool wait) {
     return rc;
 }
 
+// Evaluates the status copy in flight, if it has arrived (wait: block
+// until it has).
+int group_poll(simlod_group* g, bool wait) {
+    if (!g->status_pending) return SIMLOD_OK;
+    const hipError_t e = wait ? hipEventSynchronize(g->status_ev) : hipEventQuery(g->status_ev);
+    if (e == hipErrorNotReady) return SIMLOD_OK;
+    g->status_pending = false;
+    if (e != hipSuccess) {
+        note_error("group status event", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    return group_apply_status(g);
+}
+
 // Captures one pass (shape fixed, grid sizes from the members' capacity) on
 // the group's own stream and finds the first kernel's node.
 hipError_t group_capture(simlod_group* g, const GroupArgs& ga) {
-    const u32 cnt = (u32)g->members.size();
     hipError_t e = hipStreamBeginCapture(g->gs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t pe = enqueue_group_pass(ga, g->cap_items, g->rounds, g->shape, nullptr, g->d_status,
                                        g->gs);
-    if (pe == hipSuccess)
-        pe = hipMemcpyAsync(g->h_status, g->d_status, cnt * sizeof(u32), hipMemcpyDeviceToHost,
-                            g->gs);
     e = hipStreamEndCapture(g->gs, &g->graph);
     if (pe != hipSuccess) return pe;
     if (e != hipSuccess) return e;
@@ -1021,9 +1034,6 @@ hipError_t group_pass(simlod_group* g, const GroupArgs& ga, u64 items, hipStream
             tm = &g->tune_tm;
         }
         e = enqueue_group_pass(ga, items, g->rounds, sh, tm, g->d_status, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(g->h_status, g->d_status, cnt * sizeof(u32), hipMemcpyDeviceToHost,
-                               s);
         if (e == hipSuccess && tuning) {
             drain_timing(g->tune_tm);  // waits for this pass
             const double per = 1.0 / (double)std::max<u64>(items, 1);
@@ -1040,8 +1050,12 @@ hipError_t group_pass(simlod_group* g, const GroupArgs& ga, u64 items, hipStream
             }
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(g->status_ev, s);
-    if (e == hipSuccess) g->status_pending = true;
+    // one status copy in flight at most (the words are sticky)
+    if (e == hipSuccess && !g->status_pending) {
+        e = hipMemcpyAsync(g->h_status, g->d_status, cnt * sizeof(u32), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(g->status_ev, s);
+        if (e == hipSuccess) g->status_pending = true;
+    }
     return e;
 }
 
@@ -1082,8 +1096,8 @@ int simlod_group_create(simlod_octree* const* members, uint32_t count, uint32_t 
               hipHostMalloc((void**)&g->h_status, count * sizeof(u32), hipHostMallocDefault) ==
                   hipSuccess &&
               hipEventCreateWithFlags(&g->status_ev, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&g->join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&g->fork, kOrderingEvent) == hipSuccess &&
+              hipEventCreateWithFlags(&g->join, kOrderingEvent) == hipSuccess &&
               hipStreamCreateWithFlags(&g->gs, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         note_error("group allocation", hipGetLastError());
@@ -1127,9 +1141,9 @@ int simlod_group_insert(simlod_group* g, const simlod_point* const* pts, const u
             const u64 maxb = h->cfg.max_batch;
             const u64 off = p * maxb;
             const u64 m = off < n[i] ? std::min<u64>(maxb, n[i] - off) : 0u;
-            ga.m[i] = Member{h->d_tree,
-                             m ? reinterpret_cast<const uint4*>(pts[i] + off) : nullptr, (u32)m,
-                             (u32)(h->total_points + off)};
+            ga.m[i] = make_member(h->d_tree,
+                                  m ? reinterpret_cast<const uint4*>(pts[i] + off) : nullptr,
+                                  (u32)m, (u32)(h->total_points + off));
             items += m;
         }
         const hipError_t e = group_pass(g, ga, items, s);
@@ -1186,7 +1200,17 @@ int simlod_group_sync(simlod_group* g) {
         clear_stale_error();
         return SIMLOD_ERR_HIP;
     }
-    return group_poll(g, true);
+    int rc = group_poll(g, true);
+    if (rc) return rc;
+    // the last passes may have left no status copy: read the words
+    const hipError_t ce = hipMemcpy(g->h_status, g->d_status, g->members.size() * sizeof(u32),
+                                    hipMemcpyDeviceToHost);
+    if (ce != hipSuccess) {
+        note_error("group status read", ce);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    return group_apply_status(g);
 }
 
 int simlod_group_destroy(simlod_group* g) {
@@ -1382,7 +1406,7 @@ void server_schedule(simlod_server* sv) {
         for (u32 i = 0; i < ga.count; ++i) {
             const ServerRequest& r = ps->reqs[i];
             simlod_octree* h = sv->slots[r.slot].h;
-            ga.m[i] = Member{h->d_tree, r.pts, r.n, (u32)h->total_points};
+            ga.m[i] = make_member(h->d_tree, r.pts, r.n, (u32)h->total_points);
             h->total_points += r.n;
             h->passes += 1;
             h->last_stream = sv->stream;

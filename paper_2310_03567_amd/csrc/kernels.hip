@@ -294,6 +294,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
             u32 qx, qy, qz, depth;
             quantize3(t, batch[j], qx, qy, qz);
             leaf = find_leaf(t, qx, qy, qz, depth);
+            t.item_leaf[t.spill_cap + j] = leaf;  // the histogram round reads it
         }
         const Run r = lane_runs(leaf);
         if (leaf != kNone && r.rank == 0u) {
@@ -375,6 +376,7 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
                     const u32 o = s - ci * t.C;
                     t.spill_rec[sbase + s] = chunk_recs(t, cb)[o];
                     t.spill_key[sbase + s] = chunk_keys(t, cb)[o];
+                    t.item_leaf[sbase + s] = L;
                 }
                 const u32 nch = t.nchunks[L];
                 if (tid == 0) s_pool = atomicAdd(&ctr->pool_top, (i32)nch);
@@ -406,7 +408,7 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // root's histogram at each of the kHistLevels levels below it (levels beyond
 // Dmax do not exist).  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
-__device__ void count_hist_body(const Member* M, u32 count, u32 round) {
+__device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
@@ -433,7 +435,20 @@ __device__ void count_hist_body(const Member* M, u32 count, u32 round) {
         uint8_t* mark = (round & 1u) ? t.amask[1] : t.amask[0];
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
-        if (j < nwork && (!prev || prev[j])) {
+        if (j < nwork && !prev) {
+            // round 2: the tree has not changed since the first round, so
+            // the item's leaf is the one recorded then; only items of
+            // pending roots need their record
+            const u32 leaf = t.item_leaf[j < S ? j : t.spill_cap + (j - S)];
+            slot = t.hslot[leaf];
+            if (slot != kNone) {
+                uint4 rec;
+                u32 key;
+                fetch_work(t, M[c].batch, S, M[c].base_key, j, rec, key);
+                quantize3(t, rec, qx, qy, qz);
+                depth = t.geo[leaf].w;
+            }
+        } else if (j < nwork && prev[j]) {
             uint4 rec;
             u32 key;
             fetch_work(t, M[c].batch, S, M[c].base_key, j, rec, key);
@@ -523,7 +538,7 @@ __device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
 // descendants receive 8 consecutive children each (one node-count atomic per
 // root, in level order), occupancy grids (cleared later, in k_alloc) and
 // directory entries.
-__device__ void build_body(const Member* M, u32 count, u32 round) {
+__device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round) {
     __shared__ u32 s_h[kHistEntries];   // the root's histogram
     __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
     __shared__ u32 s_sp[kSplitSlots];   // split index of inner nodes
@@ -971,9 +986,13 @@ __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 nod
 // found within the probe limit.
 constexpr u64 kSubmitted = 1ull << 63;  // tags use bits 0..55
 
+__device__ __forceinline__ u32 cand_home(u64 tag) {
+    return (u32)(mix64(tag) >> (64u - kCandBits));
+}
+
 __device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 val,
                                             bool batch_item) {
-    u32 h = (u32)(mix64(tag) >> (64u - kCandBits));
+    u32 h = cand_home(tag);
     for (u32 p = 0; p < 64u; ++p) {
         u64 cur = ctag[h];
         if (cur != tag && (cur == kEmptyTag || (cur & kSubmitted)) &&
@@ -990,6 +1009,22 @@ __device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 v
         h = (h + 1u) & (kCands - 1u);
     }
     return false;
+}
+
+// A candidate the LDS table has no entry for is claimed in the global claim
+// table at once.
+__device__ __forceinline__ void claim_now(const DevTree& t, u64 tag, u32 key, u64 val, u32 stripe,
+                                          u32 base_key, u32* s_claims, u32* s_nclaims,
+                                          u32* s_vkey, u32* s_vcnt, u32* s_vfill) {
+    u32 home, rem, slot;
+    bool fresh;
+    claim_home(t, cell_identity(t, tag), home, rem);
+    if (claim_probe(t, home, rem, key, 0u, slot, fresh)) {
+        if (key < base_key) claim_spill_colour(t, slot, val);
+        if (fresh)
+            stage_claim(t, slot, (u32)(tag >> 24), stripe, s_claims, s_nclaims, s_vkey, s_vcnt,
+                        s_vfill);
+    }
 }
 
 // One level of voxel sampling for a wave: every lane whose node at depth d is
@@ -1014,16 +1049,9 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
-    if (cand && !cand_insert(ctag, cval, tag, val, batch_item)) {  // no entry: claim now
-        u32 home, rem, slot;
-        bool fresh;
-        claim_home(t, cell_identity(t, tag), home, rem);
-        if (claim_probe(t, home, rem, key, 0u, slot, fresh)) {
-            if (key < base_key) claim_spill_colour(t, slot, val);
-            if (fresh)
-                stage_claim(t, slot, node, stripe, s_claims, s_nclaims, s_vkey, s_vcnt, s_vfill);
-        }
-    }
+    if (cand && !cand_insert(ctag, cval, tag, val, batch_item))  // no entry: claim now
+        claim_now(t, tag, key, val, stripe, base_key, s_claims, s_nclaims, s_vkey, s_vcnt,
+                  s_vfill);
 }
 
 // Claims of one tile, in two halves so that other global atomics can share
@@ -1098,7 +1126,7 @@ constexpr u32 kNodeFlushAt = (1u << kNodeBits) / 2u;
 // Appends the workgroup's staged claims to its stripe's list (one atomic)
 // and adds its per-node new-voxel counts to the nodes (listing each node the
 // first time); leaves the LDS buffers empty.  Whole workgroup.
-__device__ void flush_staged(const DevTree& t, u32 stripe, u32* s_claims, u32* s_nclaims,
+__device__ __forceinline__ void flush_staged(const DevTree& t, u32 stripe, u32* s_claims, u32* s_nclaims,
                              u32* s_vkey, u32* s_vcnt, u32* s_vfill, u32* s_flush) {
     Counters* ctr = t.ctr;
     const u32 tid = threadIdx.x;

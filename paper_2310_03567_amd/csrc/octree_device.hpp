@@ -84,48 +84,64 @@ struct Counters {
     u64 sum_spilled, sum_new_voxels, sum_rounds;
 };
 
+// In device code the octree's tables are declared in the global address
+// space: loads, stores and atomics through them then compile to global
+// instructions rather than flat ones, which the hardware counts together
+// with LDS operations (a wait for an LDS result would also wait for every
+// outstanding memory access).  Host code sees plain pointers of the same
+// size.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using GPtr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using GPtr = T*;
+#endif
+
 struct DevTree {
     // node table
-    u32* child;
-    u32* count;
-    u32* cnt;
-    u32* hslot;          // histogram slot of a pending root, kNone otherwise
-    uint4* geo;
-    u32* grid;
-    u32* tab;
-    u32* tabcap;
-    u32* nchunks;
-    u32* newv;
+    GPtr<u32> child;
+    GPtr<u32> count;
+    GPtr<u32> cnt;
+    GPtr<u32> hslot;          // histogram slot of a pending root, kNone otherwise
+    GPtr<uint4> geo;
+    GPtr<u32> grid;
+    GPtr<u32> tab;
+    GPtr<u32> tabcap;
+    GPtr<u32> nchunks;
+    GPtr<u32> newv;
     u32 max_nodes;
-    u32* dir;
+    GPtr<u32> dir;
     u32 dir_depth;
-    Counters* ctr;
+    GPtr<Counters> ctr;
     // persistent buffer and chunk pool
-    uint8_t* arena;
+    GPtr<uint8_t> arena;
     u32 arena_blocks;
-    u32* pool;
+    GPtr<u32> pool;
     u32 pool_cap;
     // per-pass work buffers
-    uint4* spill_rec;
-    u32* spill_key;
+    GPtr<uint4> spill_rec;
+    GPtr<u32> spill_key;
     u32 spill_cap;
-    u32* touched;        // leaves counted in the first round
-    uint2* final_list;   // {leaf, points added}
-    u32* vtouched;       // inner nodes with new voxels
-    u32* pending[2];     // pending roots (leaves that must split)
-    u32* zero_list;      // grid blocks of this pass's new inner nodes
-    u32* hist;           // hist_cap slots of kHistEntries counters
+    GPtr<u32> touched;        // leaves counted in the first round
+    GPtr<uint2> final_list;   // {leaf, points added}
+    GPtr<u32> vtouched;       // inner nodes with new voxels
+    GPtr<u32> pending[2];     // pending roots (leaves that must split)
+    GPtr<u32> zero_list;      // grid blocks of this pass's new inner nodes
+    GPtr<u32> hist;           // hist_cap slots of kHistEntries counters
     u32 hist_cap;
-    uint8_t* amask[2];   // per work item: counted in the previous round
+    GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
+    GPtr<u32> item_leaf;      // per work item: its leaf in the first round (spilled
+                              // items at [0, spill_cap), batch items after)
     u32 active_cap;
-    u64* hent;           // voxel claim table, 16-byte entries (one cache line):
+    GPtr<u64> hent;           // voxel claim table, 16-byte entries (one cache line):
                          // [2h] = claim word (tag << 32 | key), min-reduced,
                          // [2h + 1] = (key << 32 | rgba) of spilled claimants,
                          // min-reduced (see claim_home)
     u32 hmask;
     u32 hash_bits;       // log2 of the claim table's entries
     u32 tag_bits;        // bits of a cell's identity node << 3r | cell
-    u32* claims;         // claim-table slots claimed this pass, kStripes x claim_cap
+    GPtr<u32> claims;         // claim-table slots claimed this pass, kStripes x claim_cap
     u32 claim_cap;
     // geometry and parameters
     float mn[3];
@@ -139,11 +155,17 @@ struct DevTree {
 // device-resident DevTree, its batch (device memory, 16-byte records) and the
 // key of the batch's first point.  A single-octree pass is a group of one.
 struct Member {
-    const DevTree* tree;
-    const uint4* batch;
+    GPtr<const DevTree> tree;
+    GPtr<const uint4> batch;
     u32 n;
     u32 base_key;
 };
+
+// Host side: a member from plain device pointers (C-style casts into the
+// device address space where the device pass declares one).
+inline Member make_member(const DevTree* tree, const uint4* batch, u32 n, u32 base_key) {
+    return Member{(GPtr<const DevTree>)tree, (GPtr<const uint4>)batch, n, base_key};
+}
 
 constexpr u32 kMaxMembers = 128;  // octrees per group pass (<= two wavefronts)
 
