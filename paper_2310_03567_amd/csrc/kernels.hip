@@ -81,18 +81,13 @@ __device__ __forceinline__ u32 cell_lin(u32 qx, u32 qy, u32 qz, u32 shift, u32 r
            (((qz >> shift) & rmask) << (2u * r));
 }
 
-// Root-to-leaf walk: the child of a node at depth d takes bit K-1-d of each
-// integer coordinate (x bit 0, y bit 1, z bit 2 of the octant).  Depths up to
-// dir_depth come from the node directory in one round of independent loads;
-// the walk continues through child[] below that.  Returns the leaf and sets
-// its depth.
-__device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 qz, u32& depth) {
+// The leaf of integer position q from its node directory entries e (depths
+// 0..dir_depth); below the directory the walk continues through child[]: the
+// child of a node at depth d takes bit K-1-d of each coordinate (x bit 0,
+// y bit 1, z bit 2 of the octant).  Sets the leaf's depth.
+__device__ __forceinline__ u32 leaf_below(const DevTree& t, const u32 (&e)[kDirMaxDepth + 1],
+                                          u32 m, u32 qx, u32 qy, u32 qz, u32& depth) {
     const u32 D = t.dir_depth;
-    const u32 m = dir_index(t.K, D, qx, qy, qz);
-    u32 e[kDirMaxDepth + 1];
-#pragma unroll
-    for (u32 d = 0; d <= kDirMaxDepth; ++d)
-        e[d] = d <= D ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
 #pragma unroll
     for (u32 d = 0; d <= kDirMaxDepth; ++d) {
         if (d <= D && !(e[d] & kDirInner)) {  // a leaf at depth d
@@ -105,7 +100,9 @@ __device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 q
             return 0u;
         }
     }
-    u32 node = e[D] & ~kDirInner;  // inner at every directory depth
+    // inner at every directory depth: e[D] again, from the directory (an
+    // index into e that is not a constant would place e in scratch memory)
+    u32 node = t.dir[dir_offset(D) + m] & ~kDirInner;
     u32 bit = t.K - 1u - D;
     u32 c = t.child[node];
     u32 d = D;
@@ -116,6 +113,25 @@ __device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 q
     }
     depth = d;
     return node;
+}
+
+// Root-to-leaf walk: the directory entries in one round of independent loads,
+// then leaf_below.
+__device__ __forceinline__ u32 find_leaf(const DevTree& t, u32 qx, u32 qy, u32 qz, u32& depth) {
+    const u32 D = t.dir_depth;
+    const u32 m = dir_index(t.K, D, qx, qy, qz);
+    u32 e[kDirMaxDepth + 1];
+#pragma unroll
+    for (u32 d = 0; d <= kDirMaxDepth; ++d)
+        e[d] = d <= D ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
+    return leaf_below(t, e, m, qx, qy, qz, depth);
+}
+
+// leaf_below without the depth.
+__device__ __forceinline__ u32 leaf_from_entries(const DevTree& t, const u32 (&e)[kDirMaxDepth + 1],
+                                                 u32 m, u32 qx, u32 qy, u32 qz) {
+    u32 depth;
+    return leaf_below(t, e, m, qx, qy, qz, depth);
 }
 
 // Workgroup-uniform early exit.  skip_if_zero (may be null): also exit when
@@ -283,18 +299,39 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
         return M[c].tree->ctr->status ? 0u : (M[c].n + kWG - 1u) / kWG;
     });
-    for (u32 tile = first_tile(); tile < ntiles;) {
+    // the tile's batch record, loaded one tile ahead
+    auto load = [&](u32 tl, uint4& rec) {
+        const u32 cc = member_of(s_pre, count, tl);
+        const u32 jj = (tl - s_pre[cc]) * kWG + tid;
+        if (jj < M[cc].n) rec = M[cc].batch[jj];
+    };
+    uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
+    u32 tile = first_tile();
+    if (tile < ntiles) load(tile, rec_n);
+    while (tile < ntiles) {
         const u32 c = member_of(s_pre, count, tile);
         const DevTree t = tree_of(M, c);
-        const uint4* batch = M[c].batch;
         const u32 n = M[c].n;
         const u32 j = (tile - s_pre[c]) * kWG + tid;
+        const uint4 rec = rec_n;
+        const u32 nx = next_tile(tile, ntiles);
         u32 leaf = kNone;
         if (j < n) {
-            u32 qx, qy, qz, depth;
-            quantize3(t, batch[j], qx, qy, qz);
-            leaf = find_leaf(t, qx, qy, qz, depth);
+            u32 qx, qy, qz;
+            quantize3(t, rec, qx, qy, qz);
+            // directory entries first, then the next tile's record, so that
+            // waiting for the entries leaves the record load in flight
+            const u32 D = t.dir_depth;
+            const u32 m = dir_index(t.K, D, qx, qy, qz);
+            u32 e[kDirMaxDepth + 1];
+#pragma unroll
+            for (u32 d = 0; d <= kDirMaxDepth; ++d)
+                e[d] = d <= D ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
+            if (nx != kNone) load(nx, rec_n);
+            leaf = leaf_from_entries(t, e, m, qx, qy, qz);
             t.item_leaf[t.spill_cap + j] = leaf;  // the histogram round reads it
+        } else if (nx != kNone) {
+            load(nx, rec_n);
         }
         const Run r = lane_runs(leaf);
         if (leaf != kNone && r.rank == 0u) {
@@ -304,7 +341,6 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
             else
                 count_leaf_global(t, leaf, r.len);
         }
-        const u32 nx = next_tile(tile, ntiles);
         count_table_tile_end(t, lkey, lval, &lfill,
                              nx == kNone || nx >= s_pre[c + 1u]);
         tile = nx;

@@ -90,12 +90,20 @@ struct Counters {
 // with LDS operations (a wait for an LDS result would also wait for every
 // outstanding memory access).  Host code sees plain pointers of the same
 // size.
+//
+// The DevTree itself is written by the host only, never while a pass runs:
+// in device code it is read through the constant address space, so that its
+// fields load with scalar instructions into scalar registers.
 #if defined(__HIP_DEVICE_COMPILE__)
 template <class T>
 using GPtr = __attribute__((address_space(1))) T*;
+template <class T>
+using CPtr = __attribute__((address_space(4))) T*;
 #else
 template <class T>
 using GPtr = T*;
+template <class T>
+using CPtr = T*;
 #endif
 
 struct DevTree {
@@ -155,7 +163,7 @@ struct DevTree {
 // device-resident DevTree, its batch (device memory, 16-byte records) and the
 // key of the batch's first point.  A single-octree pass is a group of one.
 struct Member {
-    GPtr<const DevTree> tree;
+    CPtr<const DevTree> tree;
     GPtr<const uint4> batch;
     u32 n;
     u32 base_key;
@@ -164,7 +172,7 @@ struct Member {
 // Host side: a member from plain device pointers (C-style casts into the
 // device address space where the device pass declares one).
 inline Member make_member(const DevTree* tree, const uint4* batch, u32 n, u32 base_key) {
-    return Member{(GPtr<const DevTree>)tree, (GPtr<const uint4>)batch, n, base_key};
+    return Member{(CPtr<const DevTree>)tree, (GPtr<const uint4>)batch, n, base_key};
 }
 
 constexpr u32 kMaxMembers = 128;  // octrees per group pass (<= two wavefronts)
