@@ -437,12 +437,13 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.newv, N) && dalloc(h, &t.ctr, 1) &&
               dalloc(h, &t.dir, dir_offset(t.dir_depth + 1u)) &&
               dalloc(h, &t.spill_rec, cfg->spill_capacity) &&
-              dalloc(h, &t.spill_key, cfg->spill_capacity) && dalloc(h, &t.touched, N) &&
+              dalloc(h, &t.spill_key, cfg->spill_capacity) &&
+              dalloc(h, &t.spill_job, N) && dalloc(h, &t.touched, N) &&
               dalloc(h, &t.pending[0], N) && dalloc(h, &t.pending[1], N) &&
               dalloc(h, &t.zero_list, N) &&
               dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
-              dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, work) &&
+              dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, cfg->max_batch) &&
               dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
               dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 2);  // + pass barrier words

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
                 e[d] = d <= D ? t.dir[dir_offset(d) + (m >> (3u * (D - d)))] : kNone;
             if (nx != kNone) load(nx, rec_n);
             leaf = leaf_from_entries(t, e, m, qx, qy, qz);
-            t.item_leaf[t.spill_cap + j] = leaf;  // the histogram round reads it
+            t.item_leaf[j] = leaf;  // the histogram round reads it
         } else if (nx != kNone) {
             load(nx, rec_n);
         }
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
 // the pool (section "Chunks and the Chunk Pool").  Any other counted leaf is
 // final for the pass and listed with its number of new points.
 __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count) {
-    __shared__ u32 s_dec[3];
+    __shared__ u32 s_dec[2];
     __shared__ i32 s_pool;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
@@ -375,15 +375,23 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
             if ((u64)stored + cn > (u64)t.T && depth < t.Dmax) {
                 slot = atomicAdd(&ctr->hist_top, 1u);
                 const u32 p = atomicAdd(&ctr->pending_count[1], 1u);
-                sbase = stored ? atomicAdd(&ctr->spill_count, stored) : 0u;
+                // job index and first spill index from one atomic: the jobs
+                // are listed in spill-buffer order
+                u64 sj = 0ull;
+                if (stored)
+                    sj = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr->spill_count),
+                                   (1ull << 32) | stored);
+                sbase = (u32)sj;
+                const u32 job = (u32)(sj >> 32);
                 if (slot >= t.hist_cap)
                     set_status(t, SIMLOD_OVF_HIST);
-                else if (p >= t.max_nodes)
+                else if (p >= t.max_nodes || job >= t.max_nodes)
                     set_status(t, SIMLOD_OVF_WORK);
                 else if ((u64)sbase + stored > (u64)t.spill_cap)
                     set_status(t, SIMLOD_OVF_SPILL);
                 else {
                     t.pending[1][p] = L;
+                    if (stored) t.spill_job[job] = make_uint2(L, sbase);
                     pend = 1u;
                 }
             } else {
@@ -396,24 +404,19 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
             t.cnt[L] = 0u;
             s_dec[0] = pend;
             s_dec[1] = slot;
-            s_dec[2] = sbase;
         }
         __syncthreads();
         if (s_dec[0]) {
-            const u32 slot = s_dec[1], sbase = s_dec[2];
+            const u32 slot = s_dec[1];
             u32* h = t.hist + (u64)slot * kHistEntries;
             for (u32 i = tid; i < kHistEntries; i += kWG) h[i] = 0u;
+            // The stored points are copied to the spill buffer by the
+            // histogram round (spread over its whole grid).  Their chunks
+            // go to the pool now: they are handed out again only after that
+            // round, and the node's chunk table stays as it is.
             const u32 stored = t.count[L];
             if (stored) {
                 const u32* tab = table_of(t, L);
-                for (u32 s = tid; s < stored; s += kWG) {
-                    const u32 ci = s / t.C;
-                    const u32 cb = tab[ci];
-                    const u32 o = s - ci * t.C;
-                    t.spill_rec[sbase + s] = chunk_recs(t, cb)[o];
-                    t.spill_key[sbase + s] = chunk_keys(t, cb)[o];
-                    t.item_leaf[sbase + s] = L;
-                }
                 const u32 nch = t.nchunks[L];
                 if (tid == 0) s_pool = atomicAdd(&ctr->pool_top, (i32)nch);
                 __syncthreads();
@@ -471,17 +474,37 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
         uint8_t* mark = (round & 1u) ? t.amask[1] : t.amask[0];
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
-        if (j < nwork && !prev) {
-            // round 2: the tree has not changed since the first round, so
-            // the item's leaf is the one recorded then; only items of
-            // pending roots need their record
-            const u32 leaf = t.item_leaf[j < S ? j : t.spill_cap + (j - S)];
+        if (j < S && !prev) {
+            // round 2, a spilled item: its leaf is the spill job whose range
+            // holds j (jobs are in buffer order); the record is copied from
+            // the leaf's chunks to the spill buffer for the later kernels
+            u32 lo = 0u, hi = t.ctr->spill_jobs;
+            while (hi - lo > 1u) {
+                const u32 mid = (lo + hi) >> 1;
+                if (t.spill_job[mid].y <= j)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const uint2 job = t.spill_job[lo];
+            const u32 s = j - job.y;
+            const u32 ci = s / t.C;
+            const u32 cb = table_of(t, job.x)[ci];
+            const u32 o = s - ci * t.C;
+            const uint4 rec = chunk_recs(t, cb)[o];
+            t.spill_rec[j] = rec;
+            t.spill_key[j] = chunk_keys(t, cb)[o];
+            slot = t.hslot[job.x];
+            quantize3(t, rec, qx, qy, qz);
+            depth = t.geo[job.x].w;
+        } else if (j < nwork && !prev) {
+            // round 2, a batch item: the tree has not changed since the
+            // first round, so the item's leaf is the one recorded then; only
+            // items of pending roots need their record
+            const u32 leaf = t.item_leaf[j - S];
             slot = t.hslot[leaf];
             if (slot != kNone) {
-                uint4 rec;
-                u32 key;
-                fetch_work(t, M[c].batch, S, M[c].base_key, j, rec, key);
-                quantize3(t, rec, qx, qy, qz);
+                quantize3(t, M[c].batch[j - S], qx, qy, qz);
                 depth = t.geo[leaf].w;
             }
         } else if (j < nwork && prev[j]) {
@@ -1537,6 +1560,7 @@ __global__ void k_finish(const Member* M, u32 count, u32* status_out) {
     c->sum_new_voxels += claims;
     c->sum_rounds += rounds;
     c->spill_count = 0u;
+    c->spill_jobs = 0u;
     c->final_count = 0u;
     c->vtouched_count = 0u;
     c->touched_count = 0u;

@@ -38,6 +38,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace simlod {
@@ -70,9 +71,12 @@ struct Counters {
     u32 arena_top;       // blocks handed out
     i32 pool_top;        // chunk ids on the pool stack (negative = empty)
     u32 spill_count;     // points moved to the spill buffer this pass
+    u32 spill_jobs;      // leaves spilled this pass; with spill_count one
+                         // 64-bit counter, so jobs are listed in buffer order
     u32 final_count;     // leaves finalized this pass
     u32 vtouched_count;  // inner nodes that claimed voxels this pass
     u32 touched_count;   // leaves counted in the first round
+    u32 pad0;
     u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
     u32 pending_count[2];       // pending roots listed by round k in [k & 1]
     u32 hist_top;        // histogram slots handed out this pass
@@ -83,6 +87,11 @@ struct Counters {
     u32 pad;
     u64 sum_spilled, sum_new_voxels, sum_rounds;
 };
+
+static_assert(offsetof(Counters, spill_count) % 8 == 0 &&
+                  offsetof(Counters, spill_jobs) == offsetof(Counters, spill_count) + 4,
+              "spill_count and spill_jobs form one 64-bit counter");
+static_assert(offsetof(Counters, sum_spilled) % 8 == 0, "64-bit sums aligned");
 
 // In device code the octree's tables are declared in the global address
 // space: loads, stores and atomics through them then compile to global
@@ -130,6 +139,7 @@ struct DevTree {
     // per-pass work buffers
     GPtr<uint4> spill_rec;
     GPtr<u32> spill_key;
+    GPtr<uint2> spill_job;    // {leaf, first spill index} of each spilled leaf
     u32 spill_cap;
     GPtr<u32> touched;        // leaves counted in the first round
     GPtr<uint2> final_list;   // {leaf, points added}
@@ -139,8 +149,7 @@ struct DevTree {
     GPtr<u32> hist;           // hist_cap slots of kHistEntries counters
     u32 hist_cap;
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
-    GPtr<u32> item_leaf;      // per work item: its leaf in the first round (spilled
-                              // items at [0, spill_cap), batch items after)
+    GPtr<u32> item_leaf;      // per batch item: its leaf in the first round
     u32 active_cap;
     GPtr<u64> hent;           // voxel claim table, 16-byte entries (one cache line):
                          // [2h] = claim word (tag << 32 | key), min-reduced,
