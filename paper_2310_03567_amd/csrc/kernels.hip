@@ -605,6 +605,7 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
     __shared__ u32 s_part[kWG + 1u];
     __shared__ u32 s_alloc[8];
     __shared__ u32 s_pre[kMaxMembers + 1u];
+    __shared__ u32 s_lvsplit[kHistLevels + 1u];  // level lv has a node that splits
     const u32 tid = threadIdx.x;
     const u32 total = member_prefix(count, s_pre, [&](u32 c) {
         const DevTree* tp = M[c].tree;
@@ -625,9 +626,13 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         const u32* hsrc = t.hist + (u64)t.hslot[X] * kHistEntries;
         for (u32 i = tid; i < kHistEntries; i += kWG) s_h[i] = hsrc[i];
         if (tid == 0) s_f[0] = kFExists | kFSplit;
+        if (tid <= kHistLevels) s_lvsplit[tid] = tid == 0u ? 1u : 0u;
         __syncthreads();
-        // flags, level by level (a level exists below the level above's splits)
-        for (u32 lv = 1; lv <= kHistLevels; ++lv) {
+        // flags, level by level (a level exists below the level above's
+        // splits); levels below the deepest one with nodes are not visited
+        // and the later loops stop at slot nt
+        u32 deepest = 0u;
+        for (u32 lv = 1; lv <= kHistLevels && s_lvsplit[lv - 1u]; ++lv) {  // uniform
             const u32 width = 1u << (3u * lv);
             const u32 off = hist_level_offset(lv);
             for (u32 rel = tid; rel < width; rel += kWG) {
@@ -640,17 +645,24 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
                     else if (c > 0u)
                         f |= kFFinal;
                 }
+                if (f & kFSplit) s_lvsplit[lv] = 1u;
                 s_f[1u + off + rel] = f;
             }
+            deepest = lv;
             __syncthreads();
         }
+        const u32 nt = 1u + hist_level_offset(deepest + 1u);  // slots of levels 0..deepest
+        const u32 ns = 1u + hist_level_offset(deepest);       // levels 0..deepest-1 (may split)
         // split indices (level order) and per-kind counts
-        for (u32 i = tid; i < kSplitSlots; i += kWG) s_sp[i] = (s_f[i] & kFSplit) ? 1u : 0u;
+        for (u32 i = tid; i < ns; i += kWG) s_sp[i] = (s_f[i] & kFSplit) ? 1u : 0u;
         __syncthreads();
-        const u32 nsplit = wg_exclusive_scan(s_sp, kSplitSlots, s_part);
-        for (u32 i = tid; i < kTreeSlots; i += kWG) s_q[i] = (s_f[i] & kFPending) ? 1u : 0u;
-        __syncthreads();
-        const u32 npend = wg_exclusive_scan(s_q, kTreeSlots, s_part);
+        const u32 nsplit = wg_exclusive_scan(s_sp, ns, s_part);
+        u32 npend = 0u;
+        if (deepest == kHistLevels) {  // pending roots only at the last level (uniform)
+            for (u32 i = tid; i < nt; i += kWG) s_q[i] = (s_f[i] & kFPending) ? 1u : 0u;
+            __syncthreads();
+            npend = wg_exclusive_scan(s_q, nt, s_part);
+        }
         if (tid == 0) {
             u32 ok = 1u;
             const u32 base = atomicAdd(&ctr->node_count, 8u * nsplit);
@@ -685,7 +697,7 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         const u32 hb = s_alloc[4], pb = s_alloc[5];
         const u32 xidx = d0 <= t.dir_depth ? dir_index(t.K, d0, gx.x, gx.y, gx.z) : 0u;
         // create every existing descendant (X itself already is a node)
-        for (u32 i = 1u + tid; i < kTreeSlots; i += kWG) {
+        for (u32 i = 1u + tid; i < nt; i += kWG) {
             const u32 f = s_f[i];
             if (!(f & kFExists)) continue;
             u32 lv, rel;
@@ -733,9 +745,9 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         }
         __syncthreads();
         // final leaves with their point counts
-        for (u32 i = tid; i < kTreeSlots; i += kWG) s_q[i] = (s_f[i] & kFFinal) ? 1u : 0u;
+        for (u32 i = tid; i < nt; i += kWG) s_q[i] = (s_f[i] & kFFinal) ? 1u : 0u;
         __syncthreads();
-        const u32 nfin = wg_exclusive_scan(s_q, kTreeSlots, s_part);
+        const u32 nfin = wg_exclusive_scan(s_q, nt, s_part);
         if (tid == 0) {
             const u32 fb = nfin ? atomicAdd(&ctr->final_count, nfin) : 0u;
             s_alloc[0] = (u64)fb + nfin <= (u64)t.max_nodes ? 1u : 0u;
@@ -745,7 +757,7 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         __syncthreads();
         if (!s_alloc[0]) continue;
         const u32 fb = s_alloc[6];
-        for (u32 i = 1u + tid; i < kTreeSlots; i += kWG) {
+        for (u32 i = 1u + tid; i < nt; i += kWG) {
             if (!(s_f[i] & kFFinal)) continue;
             u32 lv, rel;
             slot_level(i, lv, rel);
