@@ -189,13 +189,15 @@ typedef struct simlod_stats_data {
  * enabled by simlod_set_kernel_timing.  Index = SIMLOD_KERNEL_*. */
 #define SIMLOD_KERNEL_COUNT 0        /* expansion: first-round leaf counts */
 #define SIMLOD_KERNEL_SPLIT 1        /* expansion: first-round split        */
-#define SIMLOD_KERNEL_ALLOC_POINTS 2 /* chunk allocation for leaves         */
+#define SIMLOD_KERNEL_ALLOC_POINTS 2 /* expansion rounds 3..R (usually none) and
+                                        chunk allocation for leaves: one launch */
 #define SIMLOD_KERNEL_SAMPLE_STORE 3 /* voxel claims + point stores         */
 #define SIMLOD_KERNEL_ALLOC_VOXELS 4 /* chunk allocation for inner nodes    */
 #define SIMLOD_KERNEL_STORE_VOXELS 5 /* voxel stores                        */
 #define SIMLOD_KERNEL_FINISH 6       /* per-pass bookkeeping                */
 #define SIMLOD_KERNEL_COUNT_HIST 7   /* expansion: split histograms         */
-#define SIMLOD_KERNEL_BUILD 8        /* expansion: multi-level subtree build */
+#define SIMLOD_KERNEL_BUILD 8        /* expansion: multi-level subtree build
+                                        (round 2)                           */
 #define SIMLOD_NUM_KERNELS 9
 typedef struct simlod_kernel_times {
     uint64_t launches[SIMLOD_NUM_KERNELS];

@@ -266,11 +266,10 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
         if (e == hipSuccess)
             e = timed(tm, SIMLOD_KERNEL_BUILD, s, [&] { return launch_build(M, cnt, 2u, s); });
     }
-    if (rounds >= 3u && e == hipSuccess)  // the rare later rounds: one launch
-        e = timed(tm, SIMLOD_KERNEL_BUILD, s,
-                  [&] { return launch_rounds_tail(M, cnt, 3u, rounds, s); });
+    // the rare later rounds share the leaves' chunk allocation's launch
     if (e == hipSuccess)
-        e = timed(tm, SIMLOD_KERNEL_ALLOC_POINTS, s, [&] { return launch_alloc(M, cnt, 0u, s); });
+        e = timed(tm, SIMLOD_KERNEL_ALLOC_POINTS, s,
+                  [&] { return launch_rounds_alloc(M, cnt, 3u, rounds, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_SAMPLE_STORE, s,
                   [&] { return launch_sample_store(M, cnt, items, sh, s); });
@@ -440,7 +439,6 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.spill_key, cfg->spill_capacity) &&
               dalloc(h, &t.spill_job, N) && dalloc(h, &t.touched, N) &&
               dalloc(h, &t.pending[0], N) && dalloc(h, &t.pending[1], N) &&
-              dalloc(h, &t.zero_list, N) &&
               dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
               dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, cfg->max_batch) &&
@@ -526,6 +524,11 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     clear_stale_error();
     hipError_t re = hipMemcpy(h->d_tree, &t, sizeof(DevTree), hipMemcpyHostToDevice);
     if (re != hipSuccess) note_error("device tree copy", re);
+    // a fresh persistent buffer starts all zero (the reset clears only what
+    // earlier passes used: below the bump pointer, zero here)
+    if (re == hipSuccess) re = hipMemset(t.ctr, 0, sizeof(Counters));
+    if (re == hipSuccess) re = hipMemset(t.arena, 0, (u64)t.arena_blocks * kBlockBytes);
+    if (re != hipSuccess) note_error("initial clear", re);
     if (re == hipSuccess) re = launch_reset(t, h->hash_entries, nullptr);
     if (re != hipSuccess) note_error("reset kernels (launch)", re);
     if (re == hipSuccess) {

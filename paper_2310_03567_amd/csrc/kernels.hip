@@ -49,11 +49,12 @@ constexpr u32 kLdsBits = 11;
 constexpr u32 kLds = 1u << kLdsBits;
 constexpr u32 kHistKey = 0x80000000u;  // LDS key flag: a histogram counter
 
-// Renumbers workgroups so that each of the 8 XCDs (which receive workgroups
-// round-robin) walks a contiguous range of tiles: neighbouring points, and
-// therefore the same nodes and grid words, stay in one XCD's L2.
-__device__ __forceinline__ u32 xcd_block() {
-    u32 b = blockIdx.x, g = gridDim.x;
+// Renumbers the first g workgroups of the grid so that each of the 8 XCDs
+// (which receive workgroups round-robin) walks a contiguous range of tiles:
+// neighbouring points, and therefore the same nodes and grid words, stay in
+// one XCD's L2.
+__device__ __forceinline__ u32 xcd_block(u32 g) {
+    u32 b = blockIdx.x;
     if (g & 7u) return b;
     return (b & 7u) * (g >> 3) + (b >> 3);
 }
@@ -256,14 +257,14 @@ __device__ __forceinline__ u32 member_of(const u32* s_pre, u32 count, u32 x) {
 // workgroups in turn (XCD-aware): a workgroup meets its tiles in increasing
 // order, neighbouring tiles share nodes and cells, and dense bursts still
 // spread over all workgroups.  next_tile(tile) is the workgroup's next tile
-// after `tile`, or kNone.
+// after `tile`, or kNone.  nwg: the workgroups taking part (the first nwg).
 constexpr u32 kRunTiles = 4;
 
-__device__ __forceinline__ u32 first_tile() { return xcd_block() * kRunTiles; }
+__device__ __forceinline__ u32 first_tile(u32 nwg) { return xcd_block(nwg) * kRunTiles; }
 
-__device__ __forceinline__ u32 next_tile(u32 tile, u32 ntiles) {
+__device__ __forceinline__ u32 next_tile(u32 tile, u32 ntiles, u32 nwg) {
     const u32 nx = (tile + 1u) % kRunTiles ? tile + 1u
-                                           : tile + 1u - kRunTiles + gridDim.x * kRunTiles;
+                                           : tile + 1u - kRunTiles + nwg * kRunTiles;
     return nx < ntiles ? nx : kNone;
 }
 
@@ -287,6 +288,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     __shared__ u32 lfill;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
+    const u32 nwg = gridDim.x;
     const u32 count = ga.count;
     const Member* M = ga.m;
     if (blockIdx.x == 0 && tid < count) ga.table[tid] = M[tid];
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
         if (jj < M[cc].n) rec = M[cc].batch[jj];
     };
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
-    u32 tile = first_tile();
+    u32 tile = first_tile(nwg);
     if (tile < ntiles) load(tile, rec_n);
     while (tile < ntiles) {
         const u32 c = member_of(s_pre, count, tile);
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
         const u32 n = M[c].n;
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         const uint4 rec = rec_n;
-        const u32 nx = next_tile(tile, ntiles);
+        const u32 nx = next_tile(tile, ntiles, nwg);
         u32 leaf = kNone;
         if (j < n) {
             u32 qx, qy, qz;
@@ -447,7 +449,7 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // root's histogram at each of the kHistLevels levels below it (levels beyond
 // Dmax do not exist).  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
-__device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round) {
+__device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round, u32 nwg) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
@@ -465,7 +467,7 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
                    ? 0u
                    : (ctr->spill_count + M[c].n + kWG - 1u) / kWG;
     });
-    for (u32 tile = first_tile(); tile < ntiles;) {
+    for (u32 tile = first_tile(nwg); tile < ntiles;) {
         const u32 c = member_of(s_pre, count, tile);
         const DevTree t = tree_of(M, c);
         const u32 S = t.ctr->spill_count;
@@ -531,7 +533,7 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
                     flush_count(t, key, r.len);
             }
         }
-        const u32 nx = next_tile(tile, ntiles);
+        const u32 nx = next_tile(tile, ntiles, nwg);
         count_table_tile_end(t, lkey, lval, &lfill,
                              nx == kNone || nx >= s_pre[c + 1u]);
         tile = nx;
@@ -597,7 +599,7 @@ __device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
 // descendants receive 8 consecutive children each (one node-count atomic per
 // root, in level order), occupancy grids (cleared later, in k_alloc) and
 // directory entries.
-__device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round) {
+__device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round, u32 nwg) {
     __shared__ u32 s_h[kHistEntries];   // the root's histogram
     __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
     __shared__ u32 s_sp[kSplitSlots];   // split index of inner nodes
@@ -615,7 +617,7 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
     if (blockIdx.x == 0 && tid < count && s_pre[tid + 1u] > s_pre[tid])
         atomicAdd(&M[tid].tree->ctr->build_rounds, 1u);
     const u32 out = round & 1u;
-    for (u32 it = blockIdx.x; it < total; it += gridDim.x) {
+    for (u32 it = blockIdx.x; it < total; it += nwg) {
         const u32 c = member_of(s_pre, count, it);
         const DevTree t = tree_of(M, c);
         Counters* ctr = t.ctr;
@@ -667,7 +669,6 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
             u32 ok = 1u;
             const u32 base = atomicAdd(&ctr->node_count, 8u * nsplit);
             const u32 gbase = atomicAdd(&ctr->arena_top, nsplit * t.grid_blocks);
-            const u32 zbase = atomicAdd(&ctr->zero_count, nsplit);
             const u32 hb = npend ? atomicAdd(&ctr->hist_top, npend) : 0u;
             const u32 pb = npend ? atomicAdd(&ctr->pending_count[out], npend) : 0u;
             if ((u64)base + 8ull * nsplit > (u64)t.max_nodes) {
@@ -676,8 +677,7 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
             } else if ((u64)gbase + (u64)nsplit * t.grid_blocks > (u64)t.arena_blocks) {
                 set_status(t, SIMLOD_OVF_ARENA);
                 ok = 0u;
-            } else if ((u64)zbase + nsplit > (u64)t.max_nodes ||
-                       (u64)pb + npend > (u64)t.max_nodes) {
+            } else if ((u64)pb + npend > (u64)t.max_nodes) {
                 set_status(t, SIMLOD_OVF_WORK);
                 ok = 0u;
             } else if ((u64)hb + npend > (u64)t.hist_cap) {
@@ -687,13 +687,12 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
             s_alloc[0] = ok;
             s_alloc[1] = base;
             s_alloc[2] = gbase;
-            s_alloc[3] = zbase;
             s_alloc[4] = hb;
             s_alloc[5] = pb;
         }
         __syncthreads();
         if (!s_alloc[0]) continue;  // octree poisoned: later kernels skip it
-        const u32 base = s_alloc[1], gbase = s_alloc[2], zbase = s_alloc[3];
+        const u32 base = s_alloc[1], gbase = s_alloc[2];
         const u32 hb = s_alloc[4], pb = s_alloc[5];
         const u32 xidx = d0 <= t.dir_depth ? dir_index(t.K, d0, gx.x, gx.y, gx.z) : 0u;
         // create every existing descendant (X itself already is a node)
@@ -717,7 +716,6 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
                 const u32 g = gbase + s_sp[i] * t.grid_blocks;
                 t.child[nd] = base + 8u * s_sp[i];
                 t.grid[nd] = g;
-                t.zero_list[zbase + s_sp[i]] = g;
             } else {
                 t.child[nd] = 0u;
                 t.grid[nd] = kNone;
@@ -738,7 +736,6 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         // the root becomes inner (split index 0)
         if (tid == 0) {
             t.grid[X] = gbase;
-            t.zero_list[zbase] = gbase;
             t.hslot[X] = kNone;
             t.child[X] = base;
             if (d0 <= t.dir_depth) t.dir[dir_offset(d0) + xidx] = X | kDirInner;
@@ -769,27 +766,27 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
 }
 
 __global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round) {
-    count_hist_body(M, count, round);
+    count_hist_body(M, count, round, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 round) {
-    build_body(M, count, round);
+    build_body(M, count, round, gridDim.x);
 }
 
 constexpr u32 kBarrierSpin = 1u << 20;  // polls before a barrier gives up (~1 s)
 
-// Grid-wide barrier of a kernel whose workgroups are all resident: every
+// Barrier of the first n workgroups of a grid (all resident): every
 // workgroup releases its writes, counts itself in and waits for the
 // generation to move on.  The wait is bounded, so a grid that cannot
 // complete the barrier still exits (returns false).
-__device__ bool grid_barrier(u32* bar) {
+__device__ bool grid_barrier(u32* bar, u32 n) {
     __shared__ u32 s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const u32 gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         u32 ok = 1u;
-        if (atomicAdd(&bar[0], 1u) == gridDim.x - 1u) {
+        if (atomicAdd(&bar[0], 1u) == n - 1u) {
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -809,77 +806,15 @@ __device__ bool grid_barrier(u32* bar) {
     return s_ok != 0u;
 }
 
-// Expansion rounds first..last in one launch.  After the second round a
-// pass rarely has pending roots left (only where one pass splits a region
-// more than kHistLevels levels deep), so the kernel usually finds none and
-// exits at once, instead of six launches that each find nothing.  When
-// there are, the rounds run here, separated by grid barriers: the grid
-// (kTailWGs workgroups, at most two per CU by LDS) is all resident.  A
-// barrier that times out poisons every member of the pass.
-constexpr u32 kTailWGs = 256;
-
-__global__ __launch_bounds__(256) void k_rounds_tail(const Member* M, u32 count, u32 first,
-                                                     u32 last) {
-    __shared__ u32 s_any;
-    u32* bar = pass_barrier(M, count);
-    for (u32 round = first; round <= last; ++round) {
-        // pending roots from the round before: the same for every workgroup
-        // (written before the last barrier or launch, read after it)
-        if (threadIdx.x == 0) {
-            u32 any = 0u;
-            for (u32 c = 0; c < count && !any; ++c)
-                any = M[c].tree->ctr->pending_count[(round - 1u) & 1u] != 0u;
-            s_any = any;
-        }
-        __syncthreads();
-        if (!s_any) return;
-        count_hist_body(M, count, round);
-        bool ok = grid_barrier(bar);
-        if (ok) {
-            build_body(M, count, round);
-            ok = grid_barrier(bar);
-        }
-        if (!ok) {
-            if (threadIdx.x < count) atomicOr(&M[threadIdx.x].tree->ctr->status, SIMLOD_OVF_INTERNAL);
-            return;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- allocation
 // One wavefront per listed node: the node needs ceil((old + added) / C)
 // chunks in total (subsection "Allocating Chunks"); missing ones come from
 // the pool first, then from the persistent buffer (section "Chunks and the
 // Chunk Pool"), are appended to the node's chunk table (grown by doubling)
 // and linked after its last chunk.
-// The first call of a pass (points) also clears the occupancy grids of the
-// pass's new inner nodes, spread over the whole grid.
-constexpr u32 kZeroPiece = 4096;  // uint4 stores per workgroup visit of a new grid
-
-__global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 voxels) {
-    __shared__ u32 s_zpre[kMaxMembers + 1u];
+// nwg: the workgroups taking part (the first nwg of the grid).
+__device__ __forceinline__ void alloc_body(const Member* M, u32 count, u32 voxels, u32 nwg) {
     __shared__ u32 s_pre[kMaxMembers + 1u];
-    if (!voxels) {
-        // pieces of kZeroPiece uint4 of each new grid, one workgroup each
-        const u32 ztotal = member_prefix(count, s_zpre, [&](u32 c) {
-            const DevTree* tp = M[c].tree;
-            const u32 per = tp->grid_blocks * (kBlockBytes / 16u);
-            return tp->ctr->status ? 0u
-                                   : min(tp->ctr->zero_count, tp->max_nodes) *
-                                         ((per + kZeroPiece - 1u) / kZeroPiece);
-        });
-        for (u32 zi = blockIdx.x; zi < ztotal; zi += gridDim.x) {
-            const u32 c = member_of(s_zpre, count, zi);
-            const DevTree t = tree_of(M, c);
-            const u32 per = t.grid_blocks * (kBlockBytes / 16u);
-            const u32 pieces = (per + kZeroPiece - 1u) / kZeroPiece;
-            const u32 z = (zi - s_zpre[c]) / pieces;
-            const u32 lo = ((zi - s_zpre[c]) - z * pieces) * kZeroPiece;
-            const u32 hi = min(lo + kZeroPiece, per);
-            uint4* g = reinterpret_cast<uint4*>(block_ptr(t, t.zero_list[z]));
-            for (u32 i = lo + threadIdx.x; i < hi; i += kWG) g[i] = make_uint4(0u, 0u, 0u, 0u);
-        }
-    }
     const u32 ntotal = member_prefix(count, s_pre, [&](u32 c) {
         const DevTree* tp = M[c].tree;
         const Counters* ctr = tp->ctr;
@@ -888,7 +823,7 @@ __global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 v
     });
     const u32 lane = lane_id();
     const u32 wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
-    const u32 nwaves = gridDim.x * (kWG >> 6);
+    const u32 nwaves = nwg * (kWG >> 6);
     for (u32 ew = wave; ew < ntotal; ew += nwaves) {
         const u32 c = member_of(s_pre, count, ew);
         const DevTree t = tree_of(M, c);
@@ -963,6 +898,60 @@ __global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 v
             t.nchunks[node] = total;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 voxels) {
+    alloc_body(M, count, voxels, gridDim.x);
+}
+
+// Expansion rounds first..last, then the chunks of the final leaves, in one
+// launch.  After the second round a pass rarely has pending roots left (only
+// where one pass splits a region more than kHistLevels levels deep), so the
+// whole grid usually goes straight to the allocation, instead of launches
+// that each find nothing.  When there are, only the first kTailWGs
+// workgroups (at most two per CU by LDS, all resident once the others have
+// exited) run the rounds, separated by barriers among themselves, and then
+// the allocation.  A barrier that times out poisons every member of the pass.
+constexpr u32 kTailWGs = 256;
+
+__device__ __forceinline__ u32 any_pending(const Member* M, u32 count, u32 round) {
+    u32 any = 0u;
+    for (u32 c = 0; c < count && !any; ++c)
+        any = M[c].tree->ctr->pending_count[(round - 1u) & 1u] != 0u;
+    return any;
+}
+
+__global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count, u32 first,
+                                                      u32 last) {
+    __shared__ u32 s_any;
+    // pending roots from the round before: the same for every workgroup
+    // (written before the last barrier or launch, read after it)
+    if (threadIdx.x == 0) s_any = first <= last ? any_pending(M, count, first) : 0u;
+    __syncthreads();
+    const bool rounds = s_any != 0u;  // uniform over the grid
+    if (rounds) {
+        if (blockIdx.x >= kTailWGs) return;
+        u32* bar = pass_barrier(M, count);
+        for (u32 round = first; round <= last; ++round) {
+            if (round > first) {
+                if (threadIdx.x == 0) s_any = any_pending(M, count, round);
+                __syncthreads();
+                if (!s_any) break;  // uniform
+            }
+            count_hist_body(M, count, round, kTailWGs);
+            bool ok = grid_barrier(bar, kTailWGs);
+            if (ok) {
+                build_body(M, count, round, kTailWGs);
+                ok = grid_barrier(bar, kTailWGs);
+            }
+            if (!ok) {
+                if (threadIdx.x < count)
+                    atomicOr(&M[threadIdx.x].tree->ctr->status, SIMLOD_OVF_INTERNAL);
+                return;
+            }
+        }
+    }
+    alloc_body(M, count, 0u, rounds ? kTailWGs : gridDim.x);
 }
 
 // ------------------------------------------------------- voxel claim table
@@ -1255,6 +1244,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
     __shared__ u32 s_nclaims, s_flush, s_vfill;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
+    const u32 nwg = gridDim.x;
     for (u32 i = tid; i < kCands; i += kWG) {
         s_ctag[i] = kEmptyTag;
         s_cval[i] = ~0ull;
@@ -1284,7 +1274,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         if (j < S + M[c].n) fetch_work(*tp, M[c].batch, S, M[c].base_key, j, rec, key);
     };
-    u32 tile = first_tile();
+    u32 tile = first_tile(nwg);
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
     u32 key_n = 0u;
     if (tile < ntiles) fetch(member_of(s_pre, count, tile), tile, rec_n, key_n);
@@ -1369,7 +1359,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         // kernel) load now, so that only the chunk id waits for the slot
         const u32 nch = valid ? t.nchunks[leaf] : 0u;
         const u32* ltab = valid ? table_of(t, leaf) : nullptr;
-        const u32 nx = next_tile(tile, ntiles);
+        const u32 nx = next_tile(tile, ntiles, nwg);
         const u32 cn = nx == kNone ? kNone : member_of(s_pre, count, nx);
         __syncthreads();
         // one round trip for the tile: claim CASes, one slot reservation per
@@ -1579,7 +1569,6 @@ __global__ void k_finish(const Member* M, u32 count, u32* status_out) {
     for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
     c->pending_count[0] = c->pending_count[1] = 0u;
     c->hist_top = 0u;
-    c->zero_count = 0u;
     c->build_rounds = 0u;
 }
 
@@ -1593,6 +1582,18 @@ __global__ void k_fill_pairs(u64* p, u64 n, u64 a, u64 b) {
 __global__ void k_fill_u32(u32* p, u64 n, u32 v) {
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// Clears the blocks of the persistent buffer handed out since the last
+// reset.  Occupancy grids are only ever carved from fresh blocks (the bump
+// pointer; the pool recycles chunks only), so a buffer that is zero up to
+// the bump pointer gives every new inner node a clear grid without a pass
+// having to clear it.
+__global__ void k_zero_arena(DevTree t) {
+    const u64 n = (u64)min(t.ctr->arena_top, t.arena_blocks) * (kBlockBytes / 16u);
+    uint4* a = reinterpret_cast<uint4*>(block_ptr(t, 0u));
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+        a[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __global__ void k_reset(DevTree t) {
@@ -1701,8 +1702,9 @@ hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
     hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, m, count, round);
     return hipGetLastError();
 }
-hipError_t launch_rounds_tail(const Member* m, u32 count, u32 first, u32 last, hipStream_t s) {
-    hipLaunchKernelGGL(k_rounds_tail, dim3(kTailWGs), dim3(kWG), 0, s, m, count, first, last);
+hipError_t launch_rounds_alloc(const Member* m, u32 count, u32 first, u32 last, hipStream_t s) {
+    hipLaunchKernelGGL(k_rounds_alloc, dim3(std::max<u32>(kTailWGs, 1024u)), dim3(kWG), 0, s, m,
+                       count, first, last);
     return hipGetLastError();
 }
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
@@ -1726,6 +1728,7 @@ hipError_t launch_finish(const Member* m, u32 count, u32* status_out, hipStream_
     return hipGetLastError();
 }
 hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_arena, dim3(4096), dim3(kWG), 0, s, t);  // before the counters
     u32 g = (u32)std::min<u64>((hash_entries + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(k_fill_pairs, dim3(g), dim3(kWG), 0, s, t.hent, hash_entries, kEmptyTag,
                        ~0ull);

@@ -25,10 +25,11 @@ hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
                              const LaunchShape& sh, hipStream_t s);
 hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s);
-// Rounds first..last in one launch (exits at once when nothing is pending).
+// Rounds first..last (skipped at once when nothing is pending), then the
+// chunks of the final leaves (launch_alloc with voxels = 0), in one launch.
 // The member table must have room for two barrier words after its `count`
 // entries.
-hipError_t launch_rounds_tail(const Member* m, u32 count, u32 first, u32 last, hipStream_t s);
+hipError_t launch_rounds_alloc(const Member* m, u32 count, u32 first, u32 last, hipStream_t s);
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s);
 hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                                hipStream_t s);

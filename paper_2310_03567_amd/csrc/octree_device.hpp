@@ -80,7 +80,6 @@ struct Counters {
     u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
     u32 pending_count[2];       // pending roots listed by round k in [k & 1]
     u32 hist_top;        // histogram slots handed out this pass
-    u32 zero_count;      // occupancy grids to clear before sampling
     u32 build_rounds;    // histogram rounds that built something this pass
     u32 last_rounds, last_spilled, last_new_voxels;
     u32 max_rounds, max_spilled, max_new_voxels;
@@ -145,7 +144,6 @@ struct DevTree {
     GPtr<uint2> final_list;   // {leaf, points added}
     GPtr<u32> vtouched;       // inner nodes with new voxels
     GPtr<u32> pending[2];     // pending roots (leaves that must split)
-    GPtr<u32> zero_list;      // grid blocks of this pass's new inner nodes
     GPtr<u32> hist;           // hist_cap slots of kHistEntries counters
     u32 hist_cap;
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
