@@ -194,7 +194,9 @@ typedef struct simlod_stats_data {
 #define SIMLOD_KERNEL_SAMPLE_STORE 3 /* voxel claims + point stores         */
 #define SIMLOD_KERNEL_ALLOC_VOXELS 4 /* chunk allocation for inner nodes    */
 #define SIMLOD_KERNEL_STORE_VOXELS 5 /* voxel stores                        */
-#define SIMLOD_KERNEL_FINISH 6       /* per-pass bookkeeping                */
+#define SIMLOD_KERNEL_FINISH 6       /* group passes: status words for the
+                                        host (the bookkeeping runs in the
+                                        voxel store)                        */
 #define SIMLOD_KERNEL_COUNT_HIST 7   /* expansion: split histograms         */
 #define SIMLOD_KERNEL_BUILD 8        /* expansion: multi-level subtree build
                                         (round 2)                           */

@@ -278,7 +278,7 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_STORE_VOXELS, s,
                   [&] { return launch_store_voxels(M, cnt, items, sh, s); });
-    if (e == hipSuccess)
+    if (e == hipSuccess && status_out)  // a group's status words for the host
         e = timed(tm, SIMLOD_KERNEL_FINISH, s,
                   [&] { return launch_finish(M, cnt, status_out, s); });
     return e;

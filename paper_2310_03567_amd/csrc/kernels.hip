@@ -291,7 +291,12 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     const u32 nwg = gridDim.x;
     const u32 count = ga.count;
     const Member* M = ga.m;
-    if (blockIdx.x == 0 && tid < count) ga.table[tid] = M[tid];
+    if (blockIdx.x == 0 && tid < count) {
+        ga.table[tid] = M[tid];
+        // the previous pass's voxel store has read them: clear for this pass
+        Counters* c = M[tid].tree->ctr;
+        for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
+    }
     if (blockIdx.x == 0 && tid < 2u) pass_barrier(ga.table, count)[tid] = 0u;
     for (u32 i = tid; i < kLds; i += kWG) {
         lkey[i] = kNone;
@@ -1399,6 +1404,39 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
     }
 }
 
+// ------------------------------------------------------- bookkeeping
+// Statistics of the pass added and its counters cleared for the next one,
+// by one thread per member at the start of the voxel store kernel: none of
+// these counters is read by that kernel or written before the next pass.
+// The claim counters, which the voxel store reads, are cleared by the next
+// pass's first kernel instead.
+__device__ __forceinline__ void pass_bookkeeping(const Member& mb) {
+    const DevTree& t = *mb.tree;
+    Counters* c = t.ctr;
+    if (c->status || mb.n == 0u) return;  // an empty share did no work
+    if (c->pool_top < 0) c->pool_top = 0;
+    u32 claims = 0u;
+    for (u32 k = 0; k < kStripes; ++k) claims += min(c->claim_count[k], t.claim_cap);
+    const u32 rounds = 1u + c->build_rounds;
+    c->last_rounds = rounds;
+    c->last_spilled = c->spill_count;
+    c->last_new_voxels = claims;
+    c->max_rounds = max(c->max_rounds, rounds);
+    c->max_spilled = max(c->max_spilled, c->spill_count);
+    c->max_new_voxels = max(c->max_new_voxels, claims);
+    c->sum_spilled += c->spill_count;
+    c->sum_new_voxels += claims;
+    c->sum_rounds += rounds;
+    c->spill_count = 0u;
+    c->spill_jobs = 0u;
+    c->final_count = 0u;
+    c->vtouched_count = 0u;
+    c->touched_count = 0u;
+    c->pending_count[0] = c->pending_count[1] = 0u;
+    c->hist_top = 0u;
+    c->build_rounds = 0u;
+}
+
 // ------------------------------------------------------- voxel stores
 constexpr u32 kWordBits = 9;  // grid words touched per tile, merged in LDS
 
@@ -1413,6 +1451,7 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
     __shared__ u32 s_wbits[1u << kWordBits];
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < count) pass_bookkeeping(M[tid]);
     for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
         s_nkey[i] = kNone;
         s_ncnt[i] = 0u;
@@ -1538,38 +1577,12 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
     }
 }
 
-// ------------------------------------------------------- bookkeeping
-// One thread per member: per-pass counters cleared, statistics added.
-// status_out (may be null) receives each member's status word.
+// ------------------------------------------------------- status words
+// Group passes only: each member's status word after the pass, for the
+// host's copy.
 __global__ void k_finish(const Member* M, u32 count, u32* status_out) {
     const u32 m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= count) return;
-    const DevTree& t = *M[m].tree;
-    Counters* c = t.ctr;
-    if (status_out) status_out[m] = c->status;
-    if (c->status || M[m].n == 0u) return;  // an empty share did no work
-    if (c->pool_top < 0) c->pool_top = 0;
-    u32 claims = 0u;
-    for (u32 k = 0; k < kStripes; ++k) claims += min(c->claim_count[k], t.claim_cap);
-    const u32 rounds = 1u + c->build_rounds;
-    c->last_rounds = rounds;
-    c->last_spilled = c->spill_count;
-    c->last_new_voxels = claims;
-    c->max_rounds = max(c->max_rounds, rounds);
-    c->max_spilled = max(c->max_spilled, c->spill_count);
-    c->max_new_voxels = max(c->max_new_voxels, claims);
-    c->sum_spilled += c->spill_count;
-    c->sum_new_voxels += claims;
-    c->sum_rounds += rounds;
-    c->spill_count = 0u;
-    c->spill_jobs = 0u;
-    c->final_count = 0u;
-    c->vtouched_count = 0u;
-    c->touched_count = 0u;
-    for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
-    c->pending_count[0] = c->pending_count[1] = 0u;
-    c->hist_top = 0u;
-    c->build_rounds = 0u;
+    if (m < count) status_out[m] = M[m].tree->ctr->status;
 }
 
 // ------------------------------------------------------- reset / export
