@@ -1055,23 +1055,34 @@ __device__ __forceinline__ u32 cand_home(u64 tag) {
     return (u32)(mix64(tag) >> (64u - kCandBits));
 }
 
-__device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u64 tag, u64 val,
-                                            bool batch_item) {
+// Every probe is a compare-and-swap (from empty, or from the marker found
+// there), so the common cases (a new entry, or the cell's own) cost one LDS
+// round trip.  The lane that makes an entry live appends its index to the
+// tile's live list (live, nlive), which is all the claim step visits.
+__device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u16* live, u32* nlive, u64 tag,
+                                            u64 val, bool batch_item) {
     u32 h = cand_home(tag);
-    for (u32 p = 0; p < 64u; ++p) {
-        u64 cur = ctag[h];
-        if (cur != tag && (cur == kEmptyTag || (cur & kSubmitted)) &&
-            !(batch_item && cur == (tag | kSubmitted)))
-            cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)cur,
-                            (unsigned long long)tag) == cur
-                      ? tag
-                      : ctag[h];
+    u64 expect = kEmptyTag;
+    for (u32 p = 0; p < 64u;) {
+        const u64 cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)expect,
+                                  (unsigned long long)tag);
+        if (cur == expect) {  // made live here (from empty or from a marker)
+            live[atomicAdd(nlive, 1u)] = (u16)h;
+            atomicMin((unsigned long long*)&cval[h], (unsigned long long)val);
+            return true;
+        }
         if (cur == tag) {
             atomicMin((unsigned long long*)&cval[h], (unsigned long long)val);
             return true;
         }
-        if (batch_item && cur == (tag | kSubmitted)) return true;
-        h = (h + 1u) & (kCands - 1u);
+        if (batch_item && cur == (tag | kSubmitted)) return true;  // dominated
+        if (cur == kEmptyTag || (cur & kSubmitted)) {  // free or a marker: take it
+            expect = cur;  // entries only become live within a tile: bounded
+            continue;
+        }
+        h = (h + 1u) & (kCands - 1u);  // another cell's live entry
+        expect = kEmptyTag;
+        ++p;
     }
     return false;
 }
@@ -1101,7 +1112,8 @@ __device__ __forceinline__ void claim_now(const DevTree& t, u64 tag, u32 key, u6
 __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
                                                  u32 rgba, bool batch_item, u32 lane, u64* ctag,
-                                                 u64* cval, u32 stripe, u32 base_key,
+                                                 u64* cval, u16* s_live, u32* s_nlive,
+                                                 u32 stripe, u32 base_key,
                                                  u32* s_claims, u32* s_nclaims, u32* s_vkey,
                                                  u32* s_vcnt, u32* s_vfill) {
     u64 tag = kEmptyTag;
@@ -1114,7 +1126,7 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
-    if (cand && !cand_insert(ctag, cval, tag, val, batch_item))  // no entry: claim now
+    if (cand && !cand_insert(ctag, cval, s_live, s_nlive, tag, val, batch_item))  // no entry: claim now
         claim_now(t, tag, key, val, stripe, base_key, s_claims, s_nclaims, s_vkey, s_vcnt,
                   s_vfill);
 }
@@ -1133,20 +1145,31 @@ struct ClaimBatch {
 
 // keep: the workgroup's next tile belongs to the same octree, so submitted
 // cells stay in the table as dominance markers; otherwise it starts empty.
-__device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval, ClaimBatch& b,
+// Whole workgroup, after a barrier that follows the tile's inserts.
+__device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval,
+                                            const u16* s_live, u32 nlive, ClaimBatch& b,
                                             bool keep) {
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k) {
         const u32 i = threadIdx.x + k * 256u;
-        const u64 tg = ctag[i];
-        const bool live = tg != kEmptyTag && !(tg & kSubmitted);
-        b.tg[k] = live ? tg : kEmptyTag;
-        b.vl[k] = cval[i];
-        if (live || !keep) {
-            ctag[i] = live && keep ? (tg | kSubmitted) : kEmptyTag;
+        b.tg[k] = kEmptyTag;
+        b.vl[k] = ~0ull;
+        b.hh[k] = b.rm[k] = 0u;
+        if (i < nlive) {
+            const u32 h = s_live[i];
+            b.tg[k] = ctag[h];
+            b.vl[k] = cval[h];
+            ctag[h] = b.tg[k] | kSubmitted;
+            cval[h] = ~0ull;
+            claim_home(t, cell_identity(t, b.tg[k]), b.hh[k], b.rm[k]);
+        }
+    }
+    if (!keep) {  // uniform: every entry, markers included, cleared
+        __syncthreads();
+        for (u32 i = threadIdx.x; i < kCands; i += kWG) {
+            ctag[i] = kEmptyTag;
             cval[i] = ~0ull;
         }
-        claim_home(t, cell_identity(t, b.tg[k]), b.hh[k], b.rm[k]);
     }
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k)
@@ -1246,7 +1269,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
     __shared__ u64 s_ctag[kCands], s_cval[kCands];
-    __shared__ u32 s_nclaims, s_flush, s_vfill;
+    __shared__ u16 s_live[kCands];  // live entries of the tile's candidate table
+    __shared__ u32 s_nclaims, s_flush, s_vfill, s_nlive;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     const u32 nwg = gridDim.x;
@@ -1265,6 +1289,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
     if (tid == 0) {
         s_nclaims = 0u;
         s_vfill = 0u;
+        s_nlive = 0u;
     }
     const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
         const Counters* ctr = M[c].tree->ctr;
@@ -1328,8 +1353,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
                 desc = false;
             }
             level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w,
-                             batch_item, lane, s_ctag, s_cval, stripe, base_key, s_claims,
-                             &s_nclaims, s_vkey, s_vcnt, &s_vfill);
+                             batch_item, lane, s_ctag, s_cval, s_live, &s_nlive, stripe,
+                             base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
@@ -1345,8 +1370,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
             level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, batch_item, lane,
-                             s_ctag, s_cval, stripe, base_key, s_claims, &s_nclaims, s_vkey,
-                             s_vcnt, &s_vfill);
+                             s_ctag, s_cval, s_live, &s_nlive, stripe, base_key, s_claims,
+                             &s_nclaims, s_vkey, s_vcnt, &s_vfill);
             if (inner) node = ch + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
@@ -1370,7 +1395,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         // one round trip for the tile: claim CASes, one slot reservation per
         // leaf, and the next tile's records
         ClaimBatch cb;
-        claim_issue(t, s_ctag, s_cval, cb, cn == c);
+        claim_issue(t, s_ctag, s_cval, s_live, s_nlive, cb, cn == c);
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
@@ -1380,6 +1405,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         if (nx != kNone) fetch(cn, nx, rec_n, key_n);
         claim_resolve(t, cb, stripe, base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         __syncthreads();
+        if (tid == 0) s_nlive = 0u;  // every thread read it in claim_issue, before the barrier
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
             const u32 ci = slot / t.C;

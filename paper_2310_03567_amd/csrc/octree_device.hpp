@@ -43,6 +43,7 @@
 
 namespace simlod {
 
+typedef uint16_t u16;
 typedef uint32_t u32;
 typedef uint64_t u64;
 typedef int32_t i32;
