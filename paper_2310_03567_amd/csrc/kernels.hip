@@ -1050,6 +1050,10 @@ __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 nod
 // may be overwritten by a new live entry.  Returns false when no entry was
 // found within the probe limit.
 constexpr u64 kSubmitted = 1ull << 63;  // tags use bits 0..55
+// Probes of a candidate insert before the candidate is claimed globally at
+// once: in an overfull table (dense scans) long probe chains of atomics cost
+// more than the claim they save.
+constexpr u32 kCandProbe = 16;
 
 __device__ __forceinline__ u32 cand_home(u64 tag) {
     return (u32)(mix64(tag) >> (64u - kCandBits));
@@ -1063,7 +1067,7 @@ __device__ __forceinline__ bool cand_insert(u64* ctag, u64* cval, u16* live, u32
                                             u64 val, bool batch_item) {
     u32 h = cand_home(tag);
     u64 expect = kEmptyTag;
-    for (u32 p = 0; p < 64u;) {
+    for (u32 p = 0; p < kCandProbe;) {
         const u64 cur = atomicCAS((unsigned long long*)&ctag[h], (unsigned long long)expect,
                                   (unsigned long long)tag);
         if (cur == expect) {  // made live here (from empty or from a marker)
