@@ -1055,8 +1055,12 @@ constexpr u64 kSubmitted = 1ull << 63;  // tags use bits 0..55
 // more than the claim they save.
 constexpr u32 kCandProbe = 16;
 
+// Home entry of a cell in the LDS candidate table: a 32-bit multiplicative
+// hash of (node, cell), cheaper than a 64-bit mix; any spread will do, the
+// table only deduplicates within a workgroup.
 __device__ __forceinline__ u32 cand_home(u64 tag) {
-    return (u32)(mix64(tag) >> (64u - kCandBits));
+    const u32 x = (u32)(tag >> 24) * 0x9E3779B1u ^ (u32)tag * 0x85EBCA77u;
+    return (x ^ (x >> 15)) >> (32u - kCandBits);
 }
 
 // Every probe is a compare-and-swap (from empty, or from the marker found
