@@ -390,6 +390,7 @@ static void configure_tree(simlod_octree* h, const simlod_config* cfg, u64 arena
     t.Dmax = cfg->max_depth;
     t.T = cfg->leaf_capacity;
     t.C = cfg->chunk_capacity;
+    t.c_magic = t.C == 1u ? 0ull : ~0ull / t.C + 1ull;
     t.scale = (float)(1u << t.K) / cfg->root_size;  // float32 division
 }
 

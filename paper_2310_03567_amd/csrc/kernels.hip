@@ -495,7 +495,7 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
             }
             const uint2 job = t.spill_job[lo];
             const u32 s = j - job.y;
-            const u32 ci = s / t.C;
+            const u32 ci = div_C(t, s);
             const u32 cb = table_of(t, job.x)[ci];
             const u32 o = s - ci * t.C;
             const uint4 rec = chunk_recs(t, cb)[o];
@@ -1416,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         if (tid == 0) s_nlive = 0u;  // every thread read it in claim_issue, before the barrier
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
-            const u32 ci = slot / t.C;
+            const u32 ci = div_C(t, slot);
             if (ci < nch) {
                 const u32 cbk = ltab[ci];
                 const u32 o = slot - ci * t.C;
@@ -1591,7 +1591,7 @@ __global__ __launch_bounds__(256) void k_store_voxels(const Member* M, u32 count
             v.y = __float_as_uint(cell_centre((g.y >> shift) + cy, t.mn[1], t.size, t.r, d));
             v.z = __float_as_uint(cell_centre((g.z >> shift) + cz, t.mn[2], t.size, t.r, d));
             v.w = (u32)val;
-            const u32 ci = slot / t.C;
+            const u32 ci = div_C(t, slot);
             if (ci < nch) {
                 const u32 cb = ntab[ci];
                 const u32 o = slot - ci * t.C;
@@ -1672,7 +1672,7 @@ __global__ __launch_bounds__(256) void k_gather(DevTree t, const u32* nodes, con
         const u64 f = first[i];
         const u32* tab = table_of(t, node);
         for (u32 s = threadIdx.x; s < cnt; s += kWG) {
-            const u32 ci = s / t.C;
+            const u32 ci = div_C(t, s);
             const u32 cb = tab[ci];
             const u32 o = s - ci * t.C;
             out_rec[f + s] = chunk_recs(t, cb)[o];

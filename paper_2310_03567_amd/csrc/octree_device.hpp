@@ -164,6 +164,7 @@ struct DevTree {
     float size;
     float scale;
     u32 K, r, R, Dmax, T, C;
+    u64 c_magic;         // ceil(2^64 / C), 0 for C = 1 (see div_C)
     u32 chunk_blocks, grid_blocks, grid_words;
 };
 
@@ -269,6 +270,14 @@ __device__ __forceinline__ u32* table_of(const DevTree& t, u32 node) {
 }
 __device__ __forceinline__ u32* grid_of(const DevTree& t, u32 node) {
     return reinterpret_cast<u32*>(block_ptr(t, t.grid[node]));
+}
+
+// n / C for any n < 2^32 by one 64-bit multiply-high instead of an integer
+// division: with m = ceil(2^64 / C), n * m / 2^64 exceeds n / C by less than
+// 2^-32, too little to reach the next integer.
+__device__ __forceinline__ u32 div_C(const DevTree& t, u32 n) {
+    if (t.c_magic == 0ull) return n;  // C = 1
+    return (u32)__umul64hi((u64)n, t.c_magic);
 }
 
 // Integer coordinate along one axis.  The subtraction and the product are
