@@ -1347,13 +1347,10 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         }
         u32 leaf = kNone;
         bool desc = valid;
-        for (u32 d = 0; d <= D; ++d) {  // rolled: d is uniform, entries picked by select
-            u32 ed = e[0], wd = w[0];
 #pragma unroll
-            for (u32 k = 1; k <= kDirMaxDepth; ++k) {
-                ed = d == k ? e[k] : ed;
-                wd = d == k ? w[k] : wd;
-            }
+        for (u32 d = 0; d <= kDirMaxDepth; ++d) {  // unrolled: constant indices into e, w
+            if (d > D) break;                        // uniform
+            const u32 ed = e[d], wd = w[d];
             const bool inner = desc && ed != kNone && (ed & kDirInner);
             if (desc && !inner) {
                 if (ed == kNone) set_status(t, SIMLOD_OVF_INTERNAL);
