@@ -3,24 +3,30 @@
 //
 //   k_count_leaves, k_split_leaves   first expansion round: count the batch
 //       per leaf; a leaf whose stored plus new points exceed T (above Dmax)
-//       becomes a pending root: its stored points move to the spill buffer
-//       and it gets a histogram slot (subsection "Expanding the Octree")
-//   k_count_hist, k_build, rounds 2..R
-//       every point in a pending root adds to the root's histogram of its
-//       descendants kHistLevels levels down; the build kernel then creates
-//       that whole part of the subtree at once, and descendants at the
-//       histogram's last level that still hold more than T points become the
-//       next round's pending roots.  R = 1 + ceil(Dmax / kHistLevels) rounds
-//       always suffice; rounds without pending roots exit at once.
-//   k_alloc(points)      chunks for the leaves' new points (subsection
-//                        "Allocating Chunks"), and clearing of new grids
+//       becomes a pending root: it is listed as a spill job (its stored
+//       points are copied to the spill buffer in the next kernel) and it gets
+//       a histogram slot (subsection "Expanding the Octree")
+//   k_count_hist, k_build   round 2: every point in a pending root adds to
+//       the root's histogram of its descendants kHistLevels levels down (and
+//       spilled points are copied out of their leaf's chunks); the build
+//       kernel then creates that whole part of the subtree at once, and
+//       descendants at the histogram's last level that still hold more than
+//       T points become the next round's pending roots.  R = 1 + ceil(Dmax /
+//       kHistLevels) rounds always suffice.
+//   k_rounds_alloc       rounds 3..R, which usually find nothing to do, then
+//                        chunks for the leaves' new points (subsection
+//                        "Allocating Chunks")
 //   k_sample_store       one traversal per point: voxel claims at every
 //                        inner node on the path (subsection "Voxel Sampling")
 //                        and the point's store into its leaf (subsection
 //                        "Storing Points and Voxels")
 //   k_alloc(voxels)      chunks for the inner nodes' new voxels
-//   k_store_voxels       voxel records from the claim backlog
-//   k_finish             per-pass bookkeeping
+//   k_store_voxels       voxel records from the claim backlog, after the
+//                        pass's bookkeeping
+//   k_finish             group passes only: members' status words
+//
+// Occupancy grids need no clearing in a pass: they are carved from fresh
+// blocks of the persistent buffer, which is clear up to its bump pointer.
 //
 // The paper repeats count/split one level at a time; counting several levels
 // per round gives the same octree (a node is inner iff its region holds more
