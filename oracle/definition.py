@@ -135,54 +135,3 @@ def build(points: np.ndarray, cfg: LodConfig, keys: np.ndarray | None = None) ->
     ).astype(POINT_DTYPE, copy=False)
     allkeys = np.concatenate(key_chunks).astype(np.uint32) if key_chunks else np.empty(0, np.uint32)
     return CanonicalTree(nodes=nodes, records=records, keys=allkeys)
-
-
-def node_region_mask(points: np.ndarray, cfg: LodConfig, path: int) -> np.ndarray:
-    """Points of the cumulative sequence that fall in the node with ``path``.
-
-    Used to compute single nodes of very large octrees one by one.
-    """
-    octs = []
-    p = int(path)
-    while p > 1:
-        octs.append(p & 7)
-        p >>= 3
-    octs.reverse()
-    depth = len(octs)
-    qx = quantize(points["x"], cfg.root_min[0], cfg)
-    qy = quantize(points["y"], cfg.root_min[1], cfg)
-    qz = quantize(points["z"], cfg.root_min[2], cfg)
-    sel = np.ones(len(points), dtype=bool)
-    for d, o in enumerate(octs):
-        b = cfg.K - 1 - d
-        sel &= ((qx >> b) & 1) == (o & 1)
-        sel &= ((qy >> b) & 1) == ((o >> 1) & 1)
-        sel &= ((qz >> b) & 1) == ((o >> 2) & 1)
-    return sel, depth
-
-
-def build_node(points: np.ndarray, cfg: LodConfig, path: int):
-    """Records and keys of one node of Build(P), computed from scratch.
-
-    Returns (is_leaf, records, keys); the keys are positions in ``points``.
-    """
-    sel, depth = node_region_mask(points, cfg, path)
-    idx = np.nonzero(sel)[0]
-    if len(idx) > cfg.leaf_capacity and depth < cfg.max_depth:
-        shift = cfg.max_depth - depth
-        qx = quantize(points["x"][idx], cfg.root_min[0], cfg) >> shift
-        qy = quantize(points["y"][idx], cfg.root_min[1], cfg) >> shift
-        qz = quantize(points["z"][idx], cfg.root_min[2], cfg) >> shift
-        R = cfg.R
-        mask = np.uint32(R - 1)
-        lin = (qx & mask).astype(np.int64) + R * ((qy & mask).astype(np.int64) + R * (qz & mask).astype(np.int64))
-        _, first = np.unique(lin, return_index=True)
-        first = np.sort(first)
-        reps = idx[first]
-        vox = np.empty(len(reps), dtype=POINT_DTYPE)
-        vox["x"] = voxel_centre(qx[first], cfg.root_min[0], cfg, depth)
-        vox["y"] = voxel_centre(qy[first], cfg.root_min[1], cfg, depth)
-        vox["z"] = voxel_centre(qz[first], cfg.root_min[2], cfg, depth)
-        vox["rgba"] = points["rgba"][reps]
-        return False, vox, reps.astype(np.uint32)
-    return True, np.ascontiguousarray(points[idx]), idx.astype(np.uint32)
