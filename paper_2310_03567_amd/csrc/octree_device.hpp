@@ -380,6 +380,8 @@ __device__ __forceinline__ Run lane_runs(u32 id) {
     return r;
 }
 
+// 64-bit finalizer of Austin Appleby's MurmurHash3 (fmix64, public domain):
+// its published shift and multiplier constants.
 __device__ __forceinline__ u64 mix64(u64 x) {
     x ^= x >> 33;
     x *= 0xff51afd7ed558ccdull;

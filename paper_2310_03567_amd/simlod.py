@@ -15,8 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SIMLOD_LIBRARY selects another build of the same library (same ABI).
-LIB_PATH = os.environ.get("SIMLOD_LIBRARY") or os.path.join(_HERE, "libsimlod.so")
+# Always the in-tree build next to this file: tests and the benchmark must
+# exercise the product library, never another build of it.
+LIB_PATH = os.path.join(_HERE, "libsimlod.so")
 
 OK = 0
 ERR_INVALID_ARGUMENT = -1
@@ -88,7 +89,7 @@ class StatsData(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("max_streams", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("max_per_pass", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("staging_bytes", ctypes.c_uint64)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -100,11 +101,15 @@ EXPORTS = {
     "simlod_create": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "simlod_insert_batch": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p],
                             ctypes.c_int),
+    "simlod_insert_batch_static": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.c_void_p], ctypes.c_int),
     "simlod_snapshot": ([ctypes.c_void_p, ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_snapshot_subtree": ([ctypes.c_void_p, ctypes.c_uint64,
                                  ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_snapshot_linked": ([ctypes.c_void_p, ctypes.c_uint64,
                                 ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
+    "simlod_snapshot_node": ([ctypes.c_void_p, ctypes.c_uint64,
+                              ctypes.POINTER(SnapshotBuffers)], ctypes.c_int),
     "simlod_stats": ([ctypes.c_void_p, ctypes.POINTER(StatsData)], ctypes.c_int),
     "simlod_sync": ([ctypes.c_void_p], ctypes.c_int),
     "simlod_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -255,13 +260,26 @@ def insert_batch(handle: int, points, stream=None) -> None:
     del keep
 
 
+def insert_batch_static(handle: int, points, stream=None) -> None:
+    """simlod_insert_batch_static: host input staged through the library's
+    static device array (no device allocation in the call)."""
+    ptr, n, keep = _points_ptr(points)
+    _check(lib.simlod_insert_batch_static(handle, ptr if n else None, n, _stream_ptr(stream)),
+           "simlod_insert_batch_static")
+    del keep
+
+
 def snapshot(handle: int, path: int | None = None, nodes_only: bool = False,
-             linked: bool = False):
+             linked: bool = False, single: bool = False):
     """Canonical export: (nodes NODE_DTYPE, records POINT_DTYPE, keys uint32)
     of the whole octree, or of the subtree of the node with ``path``; with
     ``nodes_only`` the records and keys come back empty; ``linked`` reads
-    the records through the chunk lists."""
-    if linked:
+    the records through the chunk lists; ``single`` exports the node with
+    ``path`` alone."""
+    if single:
+        p = 1 if path is None else path
+        call, name = (lambda b: lib.simlod_snapshot_node(handle, p, b)), "simlod_snapshot_node"
+    elif linked:
         p = 1 if path is None else path
         call, name = (lambda b: lib.simlod_snapshot_linked(handle, p, b)), "simlod_snapshot_linked"
     elif path is None:
@@ -332,9 +350,16 @@ class Octree:
     def insert(self, points, stream=None) -> None:
         insert_batch(self.handle, points, stream)
 
+    def insert_static(self, points, stream=None) -> None:
+        insert_batch_static(self.handle, points, stream)
+
     def snapshot(self, path: int | None = None, nodes_only: bool = False,
                  linked: bool = False) -> Snapshot:
         return Snapshot(*snapshot(self.handle, path, nodes_only, linked))
+
+    def snapshot_node(self, path: int) -> Snapshot:
+        """The node with ``path`` alone (its record and its sorted records)."""
+        return Snapshot(*snapshot(self.handle, path, single=True))
 
     def stats(self) -> dict:
         return stats(self.handle)
@@ -477,12 +502,14 @@ class _ServedOctree:
 class Server:
     """Continuous-batching insertion server (``simlod_server_*``)."""
 
-    def __init__(self, max_streams: int, hbm_budget: int, max_per_pass: int = 0, device: int = 0):
+    def __init__(self, max_streams: int, hbm_budget: int, max_per_pass: int = 0, device: int = 0,
+                 staging_bytes: int = 0):
         cfg = ServerConfig(device=device, max_streams=max_streams, hbm_budget=hbm_budget,
-                           max_per_pass=max_per_pass, reserved=0)
+                           max_per_pass=max_per_pass, reserved=0, staging_bytes=staging_bytes)
         h = ctypes.c_void_p()
         _check(lib.simlod_server_create(ctypes.byref(cfg), ctypes.byref(h)), "simlod_server_create")
         self.handle = h.value
+        self._keep = {}  # ticket -> the submitted buffer, held until the request is done
 
     def open(self, cfg: Config):
         """Stream id, or None when the server is busy (no slot or budget)."""
@@ -494,10 +521,14 @@ class Server:
         return int(i.value)
 
     def submit(self, sid: int, points) -> int:
-        p, n, _ = _points_ptr(points)
+        """Queues device tensor or host array ``points`` (host memory needs a
+        server created with staging_bytes); the buffer is kept alive here
+        until the request is done."""
+        p, n, keep = _points_ptr(points)
         t = ctypes.c_uint64()
         _check(lib.simlod_server_submit(self.handle, sid, p if n else None, n, ctypes.byref(t)),
                "simlod_server_submit")
+        self._keep[int(t.value)] = keep
         return int(t.value)
 
     def poll(self, ticket: int):
@@ -505,10 +536,13 @@ class Server:
         d = ctypes.c_int()
         ms = ctypes.c_double()
         rc = lib.simlod_server_poll(self.handle, ticket, ctypes.byref(d), ctypes.byref(ms))
+        if d.value:
+            self._keep.pop(ticket, None)
         return bool(d.value), float(ms.value), int(rc)
 
     def drain(self) -> None:
         _check(lib.simlod_server_drain(self.handle), "simlod_server_drain")
+        self._keep.clear()
 
     def octree(self, sid: int) -> _ServedOctree:
         h = lib.simlod_server_octree(self.handle, sid)
