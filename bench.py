@@ -1,18 +1,22 @@
 """Insertion benchmark on one MI355X.
 
 A step is one insertion pass of the whole hot path (expand, sample, allocate,
-store) over one batch.  The default workload is the aerial-LiDAR-shaped cloud:
-100M points on a 1 km x 1 km fBm heightfield, 1M-point batches cut from
-Morton order and shuffled (seed 1), root cube [0, 1024)^3 m, T = 50,000,
+store) over one batch.  The headline workload is the aerial-LiDAR-shaped
+cloud: 100M points on a 1 km x 1 km fBm heightfield, 1M-point batches cut
+from Morton order and shuffled (seed 1), root cube [0, 1024)^3 m, T = 50,000,
 128^3 grids, Dmax = 16, chunks of 1,000.  The whole cloud is resident in HBM
 before timing starts; W warmup batches go into a scratch build that is then
 reset, and the timed region inserts batches 0..K-1 into an empty octree.
 
 Printed JSON line: points/s over the timed region, ms per step (= per 1M-point
-update), p50/p99 per-update latency from HIP events, the dominant kernel's
-roofline (algorithmic bytes per launch / its event-timed average duration,
-against 8 TB/s HBM) and the CPU oracle (sequential C inserter, one thread)
-timed on a bounded prefix of the same workload.
+update), p50/p99 per-update latency from HIP events, two rooflines against the
+8 TB/s HBM peak -- the dominant kernel's (algorithmic bytes per launch / its
+event-timed average duration) and the whole pass's (algorithmic bytes the
+insertion must move / wall-clock time of the timed region) -- the CPU oracle
+(sequential C inserter, one thread) timed on a bounded prefix of the same
+workload with the host's CPU model and core count, and, unless --no-extras,
+the same measurement on the 1B-point dense-scan workload (10M-point batches)
+and on the aerial cloud in plain Morton order and in fully random order.
 """
 
 from __future__ import annotations
@@ -68,7 +72,7 @@ SAMPLE_STORE_BYTES_PER_ITEM = 36
 SAMPLE_STORE_BYTES_PER_SPILLED = 4
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_store_aerial_hbm_traffic.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_store_{}_hbm_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03567_amd", "csrc", "kernels.hip")
 
 
@@ -76,14 +80,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per k_sample_store launch from the committed rocprofv3 summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the summary
-    was taken on a different kernel source."""
+def measured_traffic(name):
+    """HBM bytes per k_sample_store launch on workload ``name`` from the
+    committed rocprofv3 summary (FETCH_SIZE + WRITE_SIZE scaled by a plain
+    copy), or None when the summary was taken on a different kernel source."""
     import hashlib
 
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(TRAFFIC_SUMMARY.format(name)).read()
     except OSError:
         return None
     fields = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith(" "))
@@ -96,13 +100,13 @@ def measured_traffic():
         return None
 
 
-def generate(name, n=None):
+def generate(name, n=None, order=None):
     import pointgen
 
     w = WORKLOADS[name]
     n = w["points"] if n is None else n
     if name == "aerial":
-        return pointgen.aerial(n, seed=1, order="morton_shuffled", batch=w["batch"])
+        return pointgen.aerial(n, seed=1, order=order or "morton_shuffled", batch=w["batch"])
     if name == "dense":
         return pointgen.dense_scan(n, seed=2)
     return pointgen.tiny_planes(n, seed=0)
@@ -388,6 +392,23 @@ def run_chunk_sweep(args):
     print(json.dumps(result), flush=True)
 
 
+def host_facts():
+    """CPU model and thread counts of the host this runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(points, batch, cfg_kw, budget_s=20.0):
     """Sequential C oracle (one thread) on a prefix of the same batches."""
     from oracle import LodConfig
@@ -402,9 +423,145 @@ def cpu_baseline(points, batch, cfg_kw, budget_s=20.0):
         done += min(batch, len(points) - done)
     dt = time.perf_counter() - t0
     o.close()
-    return {"value": done / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done // batch} batches ({done} points) inserted in order, "
-                      f"{dt:.1f} s, sequential C inserter"}
+    out = {"value": done / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {done // batch} batches ({done} points) inserted in order, "
+                     f"{dt:.1f} s, sequential C inserter on one thread"}
+    out.update(host_facts())
+    return out
+
+
+def algorithmic_pass_bytes(points, spilled, new_voxels, new_inner):
+    """What the insertion must move, summed over the timed passes: read each
+    batch record (16 B) and write it with its key into a leaf (20 B); read
+    and rewrite each spilled record with its key (40 B); write each new
+    voxel (16 B); clear each new inner node's 128^3 occupancy grid
+    (256 KiB)."""
+    return (16 + 20) * points + 40 * spilled + 16 * new_voxels + (GRID_BYTES * new_inner)
+
+
+GRID_BYTES = 128 ** 3 // 8
+
+
+def measure(name, steps, warmup, order=None, pts=None):
+    """Times one workload: W warmup batches into a scratch build (then reset),
+    an untimed build with every kernel timed (picks the dominant kernel), the
+    timed region (batches 0..K-1 into an empty octree, the dominant kernel
+    bracketed by the library's fence-free events on the insertion stream),
+    and a build with an event pair around every pass for the per-update
+    latency.  Returns the result fields and the generated points."""
+    import torch
+
+    from paper_2310_03567_amd import simlod
+
+    w = WORKLOADS[name]
+    B = w["batch"]
+    nb_total = w["points"] // B
+    steps = min(steps, nb_total)
+    warm = min(warmup, nb_total)
+    t0 = time.perf_counter()
+    if pts is None:
+        pts = generate(name, order=order)
+    log(f"{name}{'/' + order if order else ''}: {len(pts)} points generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    need = max(steps, warm) * B
+    dev = torch.from_numpy(pts[:need].view(np.uint8).reshape(-1)).to("cuda:0")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    tree = simlod.Octree(octree_config(name))
+
+    def batch(i):
+        return dev[i * B * 16:(i + 1) * B * 16]
+
+    for i in range(warm):
+        tree.insert(batch(i), stream)
+    tree.sync()
+    tree.reset(stream)
+    simlod.set_kernel_timing(tree.handle, "all")
+    for i in range(steps):
+        tree.insert(batch(i), stream)
+    tree.sync()
+    per_kernel = simlod.get_kernel_times(tree.handle)
+    dominant = max(per_kernel, key=lambda k: per_kernel[k][1])
+    log(f"{name} per-kernel (launches, total ms): " + json.dumps(per_kernel))
+    tree.reset(stream)
+    tree.sync()
+
+    simlod.set_kernel_timing(tree.handle, [dominant])
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        tree.insert(batch(i), stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = tree.stats()
+    kt = simlod.get_kernel_times(tree.handle)[dominant]
+
+    simlod.set_kernel_timing(tree.handle, [])
+    tree.reset(stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        tree.insert(batch(i), stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    per_update_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    tree.close()
+    del dev
+    torch.cuda.empty_cache()
+
+    n_ins = steps * B
+    ms_per_step = elapsed * 1e3 / steps
+    if dominant == "sample_store" and kt[0] > 0:
+        work_items = n_ins + st["sum_spilled"]
+        alg_bytes = (SAMPLE_STORE_BYTES_PER_ITEM * work_items
+                     + SAMPLE_STORE_BYTES_PER_SPILLED * st["sum_spilled"])
+        avg_s = kt[1] / 1e3 / kt[0]
+        achieved = alg_bytes / kt[0] / avg_s / 1e9
+        traffic = measured_traffic(name)
+        roofline = {"kernel": "k_sample_store", "bound": "hbm", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else int(traffic),
+                    "launches": kt[0], "avg_launch_us": round(avg_s * 1e6, 2),
+                    "bytes_per_launch": int(alg_bytes / kt[0])}
+    else:
+        roofline = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": None, "traffic": None, "launches": kt[0],
+                    "avg_launch_us": round(kt[1] * 1e3 / max(kt[0], 1), 2)}
+    pass_bytes = algorithmic_pass_bytes(n_ins, st["sum_spilled"], st["sum_new_voxels"],
+                                        st["num_inner"])
+    pass_gbs = pass_bytes / elapsed / 1e9
+    pass_roofline = {"scope": "whole insertion pass (all kernels), wall clock of the timed "
+                              "region",
+                     "bound": "hbm", "achieved": round(pass_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(pass_gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_update": int(pass_bytes / steps),
+                     "bytes": "16+20 B per point, 40 B per spilled point, 16 B per new voxel, "
+                              "256 KiB per new inner node"}
+    kernel_us = {k: round(v[1] * 1e3 / v[0], 2) for k, v in per_kernel.items() if v[0]}
+    res = {
+        "value": round(n_ins / elapsed, 1),
+        "unit": "points/s",
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_1M_update": round(ms_per_step * 1e6 / B, 4),
+        "update_ms_p50": round(float(np.percentile(per_update_ms, 50)), 4),
+        "update_ms_p99": round(float(np.percentile(per_update_ms, 99)), 4),
+        "config": {"workload": w["desc"] + (f", order {order}" if order else ""),
+                   "points": n_ins, "batch": B,
+                   "timed_batches": f"batches 0..{steps - 1} of {nb_total} "
+                                    f"({n_ins} of {w['points']} points)",
+                   "leaf_capacity": 50_000, "grid": 128, "max_depth": 16, "chunk": 1000},
+        "octree": {k: st[k] for k in ("num_nodes", "num_inner", "num_points", "num_voxels",
+                                      "max_rounds", "sum_spilled", "sum_new_voxels")},
+        "roofline": roofline,
+        "pass_roofline": pass_roofline,
+        "kernel_avg_us": kernel_us,
+    }
+    return res, pts
 
 
 def main():
@@ -414,10 +571,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="aerial",
                     choices=sorted(WORKLOADS) + ["batched", "served", "chunk-sweep"])
-    ap.add_argument("--offered", default="1.5,6,24",
+    ap.add_argument("--order", default=None, choices=["morton_shuffled", "morton", "random"],
+                    help="aerial workload: point order of the cloud (default Morton-shuffled)")
+    ap.add_argument("--offered", default=None,
                     help="served workload: offered loads in G points/s over all streams "
-                         "(comma-separated; the last one is reported as value)")
+                         "(comma-separated); default: 0.5, 0.8 and 0.95 of the measured "
+                         "capacity of the plain (unbatched) form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only: no dense-scan and order-variant records")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (an HBM "
@@ -440,121 +602,37 @@ def main():
 
     import torch
 
-    from paper_2310_03567_amd import simlod
-
-    w = WORKLOADS[args.workload]
-    B = w["batch"]
-    nb_total = w["points"] // B
-    steps = min(args.steps, nb_total)
-    warm = min(args.warmup, nb_total)
-    t0 = time.perf_counter()
-    pts = generate(args.workload)
-    log(f"generated {len(pts)} points in {time.perf_counter() - t0:.1f} s")
-
-    dev = torch.from_numpy(pts.view(np.uint8).reshape(-1)).to("cuda:0")
-    torch.cuda.synchronize()
     if args.copy_calibration_mb:
         a = torch.empty(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    stream = torch.cuda.current_stream()
-    tree = simlod.Octree(octree_config(args.workload))
 
-    def batch(i):
-        return dev[i * B * 16:(i + 1) * B * 16]
-
-    # warmup: W batches, plus one full untimed build that times every kernel
-    for i in range(warm):
-        tree.insert(batch(i), stream)
-    tree.sync()
-    tree.reset(stream)
-    simlod.set_kernel_timing(tree.handle, "all")
-    for i in range(steps):
-        tree.insert(batch(i), stream)
-    tree.sync()
-    per_kernel = simlod.get_kernel_times(tree.handle)
-    dominant = max(per_kernel, key=lambda k: per_kernel[k][1])
-    log("per-kernel (launches, total ms): " + json.dumps(per_kernel))
-    tree.reset(stream)
-    tree.sync()
-
-    # timed region: batches 0..K-1 into an empty octree; the dominant kernel
-    # is bracketed by the library's timing events (no system-scope fence) on
-    # the insertion stream
-    simlod.set_kernel_timing(tree.handle, [dominant])
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(steps):
-        tree.insert(batch(i), stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    st = tree.stats()
-    kt = simlod.get_kernel_times(tree.handle)[dominant]
-
-    # per-update latency, in a separate build of the same batches: a torch
-    # event around every pass fences the whole system and would slow the
-    # timed region
-    simlod.set_kernel_timing(tree.handle, [])
-    tree.reset(stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    torch.cuda.synchronize()
-    for i in range(steps):
-        ev[i][0].record(stream)
-        tree.insert(batch(i), stream)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    per_update_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    tree.close()
-
-    n_ins = steps * B
-    value = n_ins / elapsed
-    ms_per_step = elapsed * 1e3 / steps
-
-    roofline = None
-    if dominant == "sample_store" and kt[0] > 0:
-        work_items = n_ins + st["sum_spilled"]
-        alg_bytes = (SAMPLE_STORE_BYTES_PER_ITEM * work_items
-                     + SAMPLE_STORE_BYTES_PER_SPILLED * st["sum_spilled"])
-        avg_s = kt[1] / 1e3 / kt[0]
-        achieved = alg_bytes / kt[0] / avg_s / 1e9
-        traffic = measured_traffic()
-        roofline = {"kernel": "k_sample_store", "bound": "hbm", "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None if traffic is None else int(traffic),
-                    "launches": kt[0], "avg_launch_us": round(avg_s * 1e6, 2),
-                    "bytes_per_launch": int(alg_bytes / kt[0])}
-    else:
-        roofline = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": None, "traffic": None, "launches": kt[0],
-                    "avg_launch_us": round(kt[1] * 1e3 / max(kt[0], 1), 2)}
-
+    name = args.workload
+    head, pts = measure(name, args.steps, args.warmup, order=args.order)
     result = {
         "metric": "inserted points/sec (ms per 1M-point update)",
-        "value": round(value, 1),
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warm,
-        "ms_per_step": round(ms_per_step, 4),
-        "ms_per_1M_update": round(ms_per_step * 1e6 / B, 4),
-        "update_ms_p50": round(float(np.percentile(per_update_ms, 50)), 4),
-        "update_ms_p99": round(float(np.percentile(per_update_ms, 99)), 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
+        "value": head["value"], "unit": "points/s", "n_gpus": 1,
+        "steps": head["steps"], "warmup": head["warmup"], "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w["desc"], "points": n_ins, "batch": B, "leaf_capacity": 50_000,
-                   "grid": 128, "max_depth": 16, "chunk": 1000},
-        "octree": {k: st[k] for k in ("num_nodes", "num_inner", "num_points", "num_voxels",
-                                      "max_rounds", "sum_spilled", "sum_new_voxels")},
-        "roofline": roofline,
     }
+    result.update({k: v for k, v in head.items() if k not in result})
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(pts, B, w, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(pts, WORKLOADS[name]["batch"], WORKLOADS[name],
+                                              args.cpu_budget)
+    del pts
+    if not args.no_extras and name == "aerial":
+        extra, _ = measure("dense", args.steps, min(args.warmup, 3))
+        result["dense"] = extra
+        if args.order is None:
+            result["order_variants"] = {}
+            for order in ("morton", "random"):
+                v, _ = measure("aerial", args.steps, args.warmup, order=order)
+                result["order_variants"][order] = {
+                    k: v[k] for k in ("value", "ms_per_step", "update_ms_p50", "update_ms_p99",
+                                      "roofline", "pass_roofline")}
     print(json.dumps(result), flush=True)
 
 

@@ -29,9 +29,11 @@
  * in a canonical order that a CPU implementation reproduces bit for bit.
  *
  * Threading and streams.  A handle must be used by one host thread at a
- * time.  Every call on a handle is ordered on the stream passed to it;
- * callers that switch streams between calls must order the streams
- * themselves.  Different handles are independent.
+ * time.  Every call on a handle is enqueued on the stream passed to it; when
+ * that is not the stream of the handle's previous call, the library first
+ * makes it wait (with an event) for everything already enqueued on the
+ * handle, so calls on one handle always run in call order.  Different
+ * handles are independent.
  *
  * Errors.  Every function returns SIMLOD_OK (0) or a negative SIMLOD_ERR_*
  * code.  Capacity overflows detected on the device (node table, persistent
@@ -218,12 +220,19 @@ typedef struct simlod_octree simlod_octree; /* opaque handle */
 int simlod_default_config(simlod_config* cfg);
 
 /* Creates an empty octree (a single empty root leaf) on cfg->device.  All
- * device memory is allocated here; inserting never allocates.  *out is
- * written only on success.  Errors: INVALID_ARGUMENT (NULL pointers,
+ * device memory is allocated here, as the paper allocates its persistent
+ * buffer once up front and carves nodes, chunks and grids out of it
+ * (section "Persistent Buffer"; leaf capacity, grid size and chunk size from
+ * section "Octree"); inserting device-resident points never allocates.
+ * The handle owns its memory until simlod_destroy.  *out is written only on
+ * success.  Errors: INVALID_ARGUMENT (NULL pointers,
  * parameters outside the ranges above), OUT_OF_MEMORY, HIP. */
 int simlod_create(const simlod_config* cfg, simlod_octree** out);
 
-/* Inserts n points (the next n keys of the cumulative sequence).
+/* Inserts n points (the next n keys of the cumulative sequence): one
+ * update of section "Incrementally Updating the Octree" per max_batch points
+ * (expand, voxel-sample, allocate and store; the paper inserts the batches
+ * loaded for a frame one after another, section "Overview").
  * pts: device or host pointer to n simlod_point records (16-byte aligned for
  * device memory); host memory is copied to a library staging buffer first.
  * The points are borrowed until the stream work completes and never
@@ -233,7 +242,28 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out);
  * POISONED, CAPACITY (an earlier pass overflowed; handle now poisoned), HIP. */
 int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, void* stream);
 
-/* Canonical export.  Synchronizes the handle's last stream.  Call with all
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * insertion as simlod_insert_batch, identical octree, but host input is
+ * staged through a static device array of the library instead of a staging
+ * buffer the library allocates, so the call never allocates or frees device
+ * memory (the passes use only buffers allocated by simlod_create).
+ * Limit: host input of at most 1,048,576 points per call (16 MiB array, one
+ * per device, held until the process ends); larger host input returns
+ * INVALID_ARGUMENT with simlod_last_error naming the limit.  Device input
+ * needs no staging and has no such limit.  All calls on one device share
+ * the array, which keeps the last call's points: calls that overlapped on a
+ * device would race on it, so the library serializes them -- a host lock per
+ * device around the staging, and on the device each call's copy into the
+ * array waits (with an event) for the passes of the previous call that read
+ * it, whatever handle, thread or stream made that call.
+ * Errors: as simlod_insert_batch, plus INVALID_ARGUMENT for the limit. */
+int simlod_insert_batch_static(simlod_octree* h, const simlod_point* pts, uint64_t n,
+                               void* stream);
+
+/* Canonical export of the whole octree: the intermediate result the paper
+ * displays while points are still streaming in (section "Introduction").
+ * Synchronizes the handle's last stream.  Call with all
  * three buffer pointers NULL to obtain the sizes, then with host buffers of
  * at least those sizes (the octree must not change in between).  With only
  * `nodes` set, fills the node records alone (no record copy).  The library
@@ -253,6 +283,13 @@ int simlod_snapshot(simlod_octree* h, simlod_snapshot_buffers* s);
  * path or is deeper than max_depth; NOT_FOUND when an ancestor of the node
  * is a leaf (the node does not exist yet). */
 int simlod_snapshot_subtree(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s);
+
+/* The export of one node alone: its node record (path, depth, leaf flag,
+ * count; first = 0) and its records sorted by key, with the same two-call
+ * pattern as simlod_snapshot; what a renderer streams for one visible node
+ * (section "Introduction": intermediate results are displayed while
+ * loading).  Errors: as simlod_snapshot_subtree. */
+int simlod_snapshot_node(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s);
 
 /* The same export read the way a renderer consumes the layout: one
  * workgroup per node starts at the node's first chunk and follows each
@@ -379,6 +416,9 @@ typedef struct simlod_server_config {
                                    1 serves requests one at a time, in
                                    arrival order: the unbatched form */
     uint32_t reserved;
+    uint64_t staging_bytes;     /* device staging for requests in host memory
+                                   (allocated at create; 0 = host requests
+                                   are rejected) */
 } simlod_server_config;
 
 int simlod_server_create(const simlod_server_config* cfg, simlod_server** out);
@@ -394,10 +434,19 @@ int simlod_config_device_bytes(const simlod_config* cfg, uint64_t* bytes);
  * *id names the stream. */
 int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id);
 
-/* Queues the insertion of pts[0..n) (16-byte-aligned device memory that the
- * caller keeps valid until the request completes) into stream id.
- * *ticket identifies the request.  Returns at once.
- * Errors: INVALID_ARGUMENT, KEY_SPACE, POISONED (the stream's octree is). */
+/* Queues the insertion of pts[0..n) into stream id; the caller keeps the
+ * points valid until the request completes.  *ticket identifies the request.
+ * Returns at once.  pts is 16-byte-aligned device memory, or host memory
+ * when the server has staging_bytes: the server's uploader thread then
+ * copies the request into the device staging area on a copy stream of its
+ * own as soon as space is free, while earlier passes run (the paper's
+ * uploader thread copies loaded batches to a GPU-side queue asynchronously,
+ * section "Overview"); the pass that takes the request waits for its copy.
+ * Pinned host memory makes the copy asynchronous; pageable memory is copied
+ * through the runtime's own staging.  A request's latency includes its
+ * upload.
+ * Errors: INVALID_ARGUMENT (also: host memory without staging, or a request
+ * larger than staging_bytes), KEY_SPACE, POISONED (the stream's octree is). */
 int simlod_server_submit(simlod_server* sv, uint32_t id, const simlod_point* pts, uint64_t n,
                          uint64_t* ticket);
 

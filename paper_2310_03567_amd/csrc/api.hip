@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -49,6 +50,8 @@ struct simlod_octree {
     hipEvent_t status_ev = nullptr;
     bool status_pending = false;
     hipStream_t last_stream = nullptr;
+    bool has_work = false;             // work was enqueued on last_stream
+    hipEvent_t order_ev = nullptr;     // orders a new stream after last_stream
     uint4* staging = nullptr;
     u64 staging_cap = 0;
     std::vector<void*> dev_allocs;
@@ -171,6 +174,7 @@ void free_all(simlod_octree* h) {
     if (h->h_status) (void)hipHostFree(h->h_status);
     h->h_status = nullptr;
     if (h->status_ev) (void)hipEventDestroy(h->status_ev);
+    if (h->order_ev) (void)hipEventDestroy(h->order_ev);
     free_timing(h->tm);
 }
 
@@ -195,6 +199,21 @@ int poll_status(simlod_octree* h, bool wait) {
         }
     }
     return SIMLOD_OK;
+}
+
+// Orders stream s after everything enqueued on the handle so far: a call on
+// another stream than the previous call's waits for that stream's work (the
+// passes share the octree's counters, claim table, spill buffers and staging
+// buffer).  Then s becomes the handle's stream.
+hipError_t order_after_last(simlod_octree* h, hipStream_t s) {
+    if (h->has_work && h->last_stream != s) {
+        hipError_t e = hipEventRecord(h->order_ev, h->last_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, h->order_ev, 0);
+        if (e != hipSuccess) return e;
+    }
+    h->last_stream = s;
+    h->has_work = true;
+    return hipSuccess;
 }
 
 hipEvent_t take_event(Timing& tm) {
@@ -510,6 +529,7 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
         ok = false;
     if (ok && hipEventCreateWithFlags(&h->status_ev, hipEventDisableTiming) != hipSuccess)
         ok = false;
+    if (ok && hipEventCreateWithFlags(&h->order_ev, kOrderingEvent) != hipSuccess) ok = false;
     if (!ok) {
         std::snprintf(g_last_error, sizeof(g_last_error), "device allocation failed (%s)",
                       hipGetErrorString(hipGetLastError()));
@@ -558,6 +578,12 @@ int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, v
     const bool dev = is_device_ptr(pts);
     if (dev && (reinterpret_cast<uintptr_t>(pts) & 15u)) return SIMLOD_ERR_INVALID_ARGUMENT;
     const u64 maxb = h->cfg.max_batch;
+    const hipError_t oe = order_after_last(h, s);
+    if (oe != hipSuccess) {
+        note_error("stream ordering", oe);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
     if (!dev && h->staging_cap < std::min<u64>(n, maxb)) {
         if (h->staging) {
             (void)hipStreamSynchronize(h->last_stream);
@@ -572,7 +598,6 @@ int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, v
         }
         h->staging_cap = cap;
     }
-    h->last_stream = s;
     u64 done = 0;
     while (done < n) {
         const u64 m = std::min<u64>(n - done, maxb);
@@ -601,6 +626,122 @@ int simlod_insert_batch(simlod_octree* h, const simlod_point* pts, uint64_t n, v
     return SIMLOD_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ static staging (no allocation)
+// simlod_insert_batch_static stages host input through this array instead of
+// a buffer the library allocates.  In host code `scratch` names only a
+// host-side stand-in: its device address, one per device (each device holds
+// its own copy of the array until the process ends), comes from
+// hipGetSymbolAddress at the device's first call and is what the copies and
+// kernels use.
+constexpr u64 kStaticStageRecords = 1ull << 20;  // 16 MiB: 1,048,576 points
+static __device__ __align__(256) uint4 scratch[kStaticStageRecords];
+
+namespace {
+
+constexpr int kMaxStageDevices = 64;
+
+struct StaticStage {
+    std::mutex mu;
+    bool ready = false;
+    uint4* ptr = nullptr;             // device address of `scratch` on this device
+    hipEvent_t free_ev = nullptr;     // after the last pass that read it
+    bool used = false;
+};
+StaticStage g_stage[kMaxStageDevices];
+
+// Set-up of device `dev` (current): the array's device address and the
+// event that orders later calls after the passes reading it.  Lock held.
+hipError_t stage_setup(StaticStage& st) {
+    if (st.ready) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&st.free_ev, kOrderingEvent);
+    if (e != hipSuccess) return e;
+    st.ptr = static_cast<uint4*>(p);
+    st.ready = true;
+    return hipSuccess;
+}
+
+// Passes over n device-resident points at src, cut at max_batch.
+int enqueue_passes(simlod_octree* h, const uint4* src, u64 n, hipStream_t s) {
+    const u64 maxb = h->cfg.max_batch;
+    for (u64 done = 0; done < n;) {
+        const u64 m = std::min<u64>(n - done, maxb);
+        const hipError_t pe = enqueue_pass(h, src + done, (u32)m, (u32)h->total_points, s);
+        if (pe != hipSuccess) {
+            note_error("insertion pass launch", pe);
+            clear_stale_error();
+            h->poisoned = 1;
+            h->sticky = SIMLOD_ERR_HIP;
+            return SIMLOD_ERR_HIP;
+        }
+        h->total_points += m;
+        h->passes += 1;
+        done += m;
+    }
+    return SIMLOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int simlod_insert_batch_static(simlod_octree* h, const simlod_point* pts, uint64_t n,
+                               void* stream) {
+    if (!h || (n && !pts)) return SIMLOD_ERR_INVALID_ARGUMENT;
+    DeviceGuard guard(h->device);
+    int rc = poll_status(h, false);
+    if (rc) return rc;
+    if (n == 0) return SIMLOD_OK;
+    clear_stale_error();
+    if (h->total_points + n > 0xFFFFFFFFull) return SIMLOD_ERR_KEY_SPACE;
+    if (h->device < 0 || h->device >= kMaxStageDevices) return SIMLOD_ERR_INVALID_ARGUMENT;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool dev = is_device_ptr(pts);
+    if (dev && (reinterpret_cast<uintptr_t>(pts) & 15u)) return SIMLOD_ERR_INVALID_ARGUMENT;
+    if (!dev && n > kStaticStageRecords) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "host input of %llu points exceeds the static staging buffer (%llu points)",
+                      (unsigned long long)n, (unsigned long long)kStaticStageRecords);
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
+    hipError_t e = order_after_last(h, s);
+    if (e != hipSuccess) {
+        note_error("stream ordering", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    if (dev) return enqueue_passes(h, reinterpret_cast<const uint4*>(pts), n, s);
+    StaticStage& st = g_stage[h->device];
+    std::lock_guard<std::mutex> lk(st.mu);
+    e = stage_setup(st);
+    if (e != hipSuccess) {
+        note_error("static staging set-up", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    // the previous call's passes on this device must have read the array
+    if (st.used) e = hipStreamWaitEvent(s, st.free_ev, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.ptr, pts, n * 16ull, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        note_error("host-to-device copy", e);
+        clear_stale_error();
+        return SIMLOD_ERR_HIP;
+    }
+    rc = enqueue_passes(h, st.ptr, n, s);
+    e = hipEventRecord(st.free_ev, s);
+    if (e != hipSuccess) {
+        note_error("static staging event", e);
+        clear_stale_error();
+        return rc ? rc : SIMLOD_ERR_HIP;
+    }
+    st.used = true;
+    return rc;
+}
+
 int simlod_sync(simlod_octree* h) {
     if (!h) return SIMLOD_ERR_INVALID_ARGUMENT;
     DeviceGuard guard(h->device);
@@ -611,9 +752,10 @@ int simlod_sync(simlod_octree* h) {
 namespace {
 
 // Canonical export of the subtree rooted at the node with `root_path`;
-// linked: read every node through its chunk list instead of its chunk table.
+// linked: read every node through its chunk list instead of its chunk table;
+// single: that node alone, without its descendants.
 int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s,
-                   bool linked = false) {
+                   bool linked = false, bool single = false) {
     if (!h || !s) return SIMLOD_ERR_INVALID_ARGUMENT;
     const int nulls = (s->nodes == nullptr) + (s->records == nullptr) + (s->keys == nullptr);
     const bool nodes_only = nulls == 2 && s->nodes != nullptr;
@@ -670,7 +812,7 @@ int export_subtree(simlod_octree* h, u64 root_path, simlod_snapshot_buffers* s,
         path.push_back(p);
         written += hn.count[node];
         (hn.child[node] ? nvox : npts) += hn.count[node];
-        if (hn.child[node])
+        if (hn.child[node] && !single)
             for (int o = 7; o >= 0; --o) stack.push_back({hn.child[node] + (u32)o, p * 8 + (u64)o});
     }
     const u32 ns = (u32)order.size();
@@ -796,6 +938,10 @@ int simlod_snapshot_linked(simlod_octree* h, uint64_t path, simlod_snapshot_buff
     return export_subtree(h, path, s, true);
 }
 
+int simlod_snapshot_node(simlod_octree* h, uint64_t path, simlod_snapshot_buffers* s) {
+    return export_subtree(h, path, s, false, true);
+}
+
 int simlod_stats(simlod_octree* h, simlod_stats_data* st) {
     if (!h || !st) return SIMLOD_ERR_INVALID_ARGUMENT;
     DeviceGuard guard(h->device);
@@ -841,13 +987,13 @@ int simlod_reset(simlod_octree* h, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (h->poisoned) (void)hipStreamSynchronize(h->last_stream);
     clear_stale_error();
-    const hipError_t re = launch_reset(h->t, h->hash_entries, s);
+    hipError_t re = order_after_last(h, s);
+    if (re == hipSuccess) re = launch_reset(h->t, h->hash_entries, s);
     if (re != hipSuccess) {
         note_error("reset kernels (launch)", re);
         clear_stale_error();
         return SIMLOD_ERR_HIP;
     }
-    h->last_stream = s;
     h->total_points = 0;
     h->passes = 0;
     h->poisoned = 0;
@@ -1136,6 +1282,14 @@ int simlod_group_insert(simlod_group* g, const simlod_point* const* pts, const u
     }
     clear_stale_error();
     hipStream_t s = static_cast<hipStream_t>(stream);
+    for (u32 i = 0; i < cnt && passes; ++i) {
+        const hipError_t oe = order_after_last(g->members[i], s);
+        if (oe != hipSuccess) {
+            note_error("stream ordering", oe);
+            clear_stale_error();
+            return SIMLOD_ERR_HIP;
+        }
+    }
     for (u64 p = 0; p < passes; ++p) {
         GroupArgs ga{};
         ga.table = g->d_table;
@@ -1164,7 +1318,6 @@ int simlod_group_insert(simlod_group* g, const simlod_point* const* pts, const u
     }
     for (u32 i = 0; i < cnt; ++i) {
         simlod_octree* h = g->members[i];
-        h->last_stream = s;
         h->total_points += n[i];
         h->passes += (n[i] + h->cfg.max_batch - 1) / h->cfg.max_batch;
     }
@@ -1284,9 +1437,13 @@ constexpr u32 kStatusRing = 4;      // pinned status arrays, > kServerInflight
 struct ServerRequest {
     u64 ticket;
     u32 slot;
-    const uint4* pts;
+    const uint4* pts;             // device points (staging area for host requests)
     u32 n;
     Clock::time_point t_submit;
+    const void* host = nullptr;   // host points, for requests in host memory
+    bool ready = true;            // host requests: the copy has been enqueued
+    u64 stage_off = 0, stage_len = 0;  // staging range of a host request
+    hipEvent_t up_ev = nullptr;   // host requests: after the copy
 };
 
 struct ServerSlot {
@@ -1315,6 +1472,15 @@ struct RequestResult {
 struct simlod_server {
     simlod_server_config cfg{};
     std::mutex mu;
+    // uploads of requests in host memory (section "Overview": an uploader
+    // thread copies loaded batches to a GPU-side queue)
+    uint8_t* staging = nullptr;       // staging_bytes of device memory
+    std::map<u64, u64> stage_free;    // free ranges: offset -> length
+    std::deque<u64> upload_q;         // tickets of host requests to copy, in order
+    std::condition_variable cv_upload;
+    hipStream_t copy_stream = nullptr;
+    std::vector<hipEvent_t> free_up_events;
+    std::thread uploader;
     std::condition_variable cv_work;  // scheduler: requests queued or a pass retired
     std::condition_variable cv_done;  // callers: requests completed
     std::condition_variable cv_retire;  // completion thread: a pass was enqueued
@@ -1342,21 +1508,140 @@ struct simlod_server {
 
 namespace {
 
+constexpr u64 kStageAlign = 256;
+
+// Staging ranges for requests in host memory: first fit over the free
+// ranges (lock held).
+bool stage_alloc(simlod_server* sv, u64 len, u64* off) {
+    for (auto it = sv->stage_free.begin(); it != sv->stage_free.end(); ++it) {
+        if (it->second < len) continue;
+        *off = it->first;
+        const u64 rest = it->second - len, at = it->first + len;
+        sv->stage_free.erase(it);
+        if (rest) sv->stage_free[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+void stage_release(simlod_server* sv, u64 off, u64 len) {
+    auto it = sv->stage_free.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != sv->stage_free.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        sv->stage_free.erase(nx);
+    }
+    if (it != sv->stage_free.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            sv->stage_free.erase(it);
+        }
+    }
+}
+
+// A host request's staging range and event go back once its copy is done
+// (lock held; the copy has completed or completes shortly).
+void release_upload(simlod_server* sv, ServerRequest& r) {
+    if (!r.stage_len) return;
+    if (r.up_ev) {
+        (void)hipEventSynchronize(r.up_ev);
+        sv->free_up_events.push_back(r.up_ev);
+    }
+    stage_release(sv, r.stage_off, r.stage_len);
+    r.stage_len = 0;
+    r.up_ev = nullptr;
+    sv->cv_upload.notify_all();
+}
+
+ServerRequest* find_queued(simlod_server* sv, u64 ticket) {
+    for (ServerSlot& sl : sv->slots)
+        for (ServerRequest& r : sl.queue)
+            if (r.ticket == ticket) return &r;
+    return nullptr;
+}
+
+// Uploader thread: copies the requests in host memory, in submission order,
+// into free staging ranges on the server's copy stream, while the passes of
+// earlier requests run on the pass stream; a request becomes eligible for a
+// pass once its copy is enqueued, and the pass waits for the copy's event.
+void server_upload(simlod_server* sv) {
+    (void)hipSetDevice(sv->cfg.device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_upload.wait(lk, [&] { return sv->stop || !sv->upload_q.empty(); });
+        if (sv->stop) return;
+        const u64 tk = sv->upload_q.front();
+        ServerRequest* r = find_queued(sv, tk);
+        if (!r) {  // its stream was poisoned and its requests completed
+            sv->upload_q.pop_front();
+            continue;
+        }
+        const u64 len = ((u64)r->n * 16u + kStageAlign - 1) / kStageAlign * kStageAlign;
+        u64 off = 0;
+        if (!stage_alloc(sv, len, &off)) {  // wait until completed passes free space
+            sv->cv_upload.wait(lk);
+            continue;
+        }
+        sv->upload_q.pop_front();
+        hipEvent_t ev = nullptr;
+        if (!sv->free_up_events.empty()) {
+            ev = sv->free_up_events.back();
+            sv->free_up_events.pop_back();
+        } else {
+            (void)hipEventCreateWithFlags(&ev, kOrderingEvent);
+        }
+        r->stage_off = off;
+        r->stage_len = len;
+        r->up_ev = ev;
+        const void* src = r->host;
+        const u64 bytes = (u64)r->n * 16u;
+        lk.unlock();
+        hipError_t e = hipMemcpyAsync(sv->staging + off, src, bytes, hipMemcpyHostToDevice,
+                                      sv->copy_stream);
+        if (e == hipSuccess) e = hipEventRecord(ev, sv->copy_stream);
+        lk.lock();
+        r = find_queued(sv, tk);
+        if (!r) {  // completed as poisoned meanwhile: the range is ours to free
+            ServerRequest gone{};
+            gone.stage_off = off;
+            gone.stage_len = len;
+            gone.up_ev = ev;
+            release_upload(sv, gone);
+            continue;
+        }
+        if (e != hipSuccess) {
+            note_error("server upload", e);
+            (void)hipGetLastError();
+            simlod_octree* h = sv->slots[r->slot].h;
+            if (h && !h->poisoned) {
+                h->poisoned = 1;
+                h->sticky = SIMLOD_ERR_HIP;
+            }
+        }
+        r->pts = reinterpret_cast<const uint4*>(sv->staging + off);
+        r->ready = true;
+        sv->cv_work.notify_all();
+    }
+}
+
 // Chooses the next pass's requests (lock held): the head request of every
-// open stream that has one (max_per_pass 0), else the max_per_pass oldest
-// heads.  Requests of poisoned streams complete at once with POISONED.
+// open stream that has one ready (max_per_pass 0), else the max_per_pass
+// oldest ready heads.  Requests of poisoned streams complete at once with
+// POISONED.
 std::vector<ServerRequest> server_pick(simlod_server* sv) {
     std::vector<u32> heads;
     for (u32 i = 0; i < sv->slots.size(); ++i) {
         ServerSlot& sl = sv->slots[i];
         while (!sl.queue.empty() && (sl.h == nullptr || sl.h->poisoned)) {
-            const ServerRequest& r = sl.queue.front();
+            ServerRequest& r = sl.queue.front();
             sv->results[r.ticket - 1] = RequestResult{1, SIMLOD_ERR_POISONED, 0.0};
+            if (r.ready) release_upload(sv, r);  // else the uploader frees it
             sl.queued_points -= r.n;
             sl.queue.pop_front();
             ++sv->completed;
         }
-        if (!sl.queue.empty()) heads.push_back(i);
+        if (!sl.queue.empty() && sl.queue.front().ready) heads.push_back(i);
     }
     const u32 lim = sv->cfg.max_per_pass ? sv->cfg.max_per_pass : kMaxMembers;
     if (heads.size() > lim) {
@@ -1384,7 +1669,9 @@ void server_schedule(simlod_server* sv) {
             if (sv->stop) return true;
             if (sv->inflight.size() >= kServerInflight) return false;
             for (const ServerSlot& sl : sv->slots)
-                if (!sl.queue.empty()) return true;
+                if (!sl.queue.empty() &&
+                    (sl.queue.front().ready || sl.h == nullptr || sl.h->poisoned))
+                    return true;
             return false;
         });
         if (sv->stop) return;
@@ -1415,13 +1702,18 @@ void server_schedule(simlod_server* sv) {
             h->total_points += r.n;
             h->passes += 1;
             h->last_stream = sv->stream;
+            h->has_work = true;
             items += r.n;
             rounds = std::max(rounds, expansion_rounds(h->cfg.max_depth));
         }
         u32* hs = sv->h_status + (u64)ps->ring * kMaxMembers;
         std::memset(hs, 0, ga.count * sizeof(u32));
-        hipError_t e = enqueue_group_pass(ga, items, rounds, default_shape(), nullptr,
-                                          sv->d_status, sv->stream);
+        hipError_t e = hipSuccess;
+        for (const ServerRequest& r : ps->reqs)  // uploads of host requests first
+            if (e == hipSuccess && r.up_ev) e = hipStreamWaitEvent(sv->stream, r.up_ev, 0);
+        if (e == hipSuccess)
+            e = enqueue_group_pass(ga, items, rounds, default_shape(), nullptr, sv->d_status,
+                                   sv->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hs, sv->d_status, ga.count * sizeof(u32), hipMemcpyDeviceToHost,
                                sv->stream);
@@ -1474,6 +1766,7 @@ void server_complete(simlod_server* sv) {
             sv->results[r.ticket - 1] = RequestResult{1, st, ms};
             sl.inflight -= 1;
             ++sv->completed;
+            if (r.stage_len) release_upload(sv, ps->reqs[i]);
         }
         sv->free_events.push_back(ps->done);
         delete ps;
@@ -1553,9 +1846,15 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
               hipMalloc((void**)&sv->d_status, kMaxMembers * sizeof(u32)) == hipSuccess &&
               hipHostMalloc((void**)&sv->h_status, kStatusRing * kMaxMembers * sizeof(u32),
                             hipHostMallocDefault) == hipSuccess;
+    const u64 stage = cfg->staging_bytes / kStageAlign * kStageAlign;
+    if (ok && stage)
+        ok = hipMalloc((void**)&sv->staging, stage) == hipSuccess &&
+             hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         note_error("server allocation", hipGetLastError());
         clear_stale_error();
+        if (sv->staging) (void)hipFree(sv->staging);
+        if (sv->copy_stream) (void)hipStreamDestroy(sv->copy_stream);
         if (sv->stream) (void)hipStreamDestroy(sv->stream);
         if (sv->d_table) (void)hipFree(sv->d_table);
         if (sv->d_status) (void)hipFree(sv->d_status);
@@ -1563,9 +1862,11 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
         delete sv;
         return SIMLOD_ERR_OUT_OF_MEMORY;
     }
+    if (stage) sv->stage_free[0] = stage;
     sv->scheduler = std::thread(server_schedule, sv);
     sv->completer = std::thread(server_complete, sv);
     sv->reaper = std::thread(server_reap, sv);
+    if (stage) sv->uploader = std::thread(server_upload, sv);
     *out = sv;
     return SIMLOD_OK;
 }
@@ -1631,6 +1932,7 @@ int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id
         h->sticky = SIMLOD_OK;
         h->status_pending = false;
         h->last_stream = sv->stream;
+        h->has_work = true;
         if (e != hipSuccess) {
             note_error("pooled octree reset", e);
             clear_stale_error();
@@ -1663,9 +1965,14 @@ int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id
 int simlod_server_submit(simlod_server* sv, uint32_t id, const simlod_point* pts, uint64_t n,
                          uint64_t* ticket) {
     if (!sv || !ticket || (n && !pts)) return SIMLOD_ERR_INVALID_ARGUMENT;
-    if (n && ((reinterpret_cast<uintptr_t>(pts) & 15u) || !is_device_ptr(pts))) {
+    bool on_host = false;
+    if (n) {
+        DeviceGuard guard(sv->cfg.device);
+        on_host = !is_device_ptr(pts);
         clear_stale_error();
-        return SIMLOD_ERR_INVALID_ARGUMENT;
+        if (on_host ? (!sv->staging || n * 16u > sv->cfg.staging_bytes / kStageAlign * kStageAlign)
+                    : (reinterpret_cast<uintptr_t>(pts) & 15u) != 0u)
+            return SIMLOD_ERR_INVALID_ARGUMENT;
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     if (id >= sv->slots.size() || !sv->slots[id].open || sv->slots[id].closing)
@@ -1683,8 +1990,15 @@ int simlod_server_submit(simlod_server* sv, uint32_t id, const simlod_point* pts
         ++sv->completed;
         return SIMLOD_OK;
     }
-    sl.queue.push_back(ServerRequest{t, id, reinterpret_cast<const uint4*>(pts), (u32)n,
-                                     Clock::now()});
+    ServerRequest rq{t, id, reinterpret_cast<const uint4*>(pts), (u32)n, Clock::now()};
+    if (on_host) {
+        rq.pts = nullptr;
+        rq.host = pts;
+        rq.ready = false;
+        sv->upload_q.push_back(t);
+        sv->cv_upload.notify_one();
+    }
+    sl.queue.push_back(rq);
     sl.queued_points += n;
     sv->cv_work.notify_one();
     return SIMLOD_OK;
@@ -1758,9 +2072,11 @@ int simlod_server_destroy(simlod_server* sv) {
     sv->cv_work.notify_all();
     sv->cv_retire.notify_all();
     sv->cv_reap.notify_all();
+    sv->cv_upload.notify_all();
     sv->scheduler.join();
     sv->completer.join();
     sv->reaper.join();
+    if (sv->uploader.joinable()) sv->uploader.join();
     DeviceGuard guard(sv->cfg.device);
     (void)hipStreamSynchronize(sv->stream);
     int rc = SIMLOD_OK;
@@ -1769,6 +2085,10 @@ int simlod_server_destroy(simlod_server* sv) {
     for (auto& p : sv->pool)
         if (simlod_destroy(p.h) != SIMLOD_OK) rc = SIMLOD_ERR_HIP;
     for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : sv->free_up_events) (void)hipEventDestroy(e);
+    if (sv->copy_stream) (void)hipStreamSynchronize(sv->copy_stream);
+    if (sv->copy_stream) (void)hipStreamDestroy(sv->copy_stream);
+    if (sv->staging) (void)hipFree(sv->staging);
     (void)hipStreamDestroy(sv->stream);
     (void)hipFree(sv->d_table);
     (void)hipFree(sv->d_status);

@@ -608,8 +608,8 @@ __device__ __forceinline__ u32 slot_parent(u32 lv, u32 rel) {
 // next round (with a fresh histogram slot); every other descendant with
 // points is a final leaf listed with its point count.  X and its inner
 // descendants receive 8 consecutive children each (one node-count atomic per
-// root, in level order), occupancy grids (cleared later, in k_alloc) and
-// directory entries.
+// root, in level order), occupancy grids (fresh blocks of the persistent
+// buffer, which is clear above its bump pointer) and directory entries.
 __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round, u32 nwg) {
     __shared__ u32 s_h[kHistEntries];   // the root's histogram
     __shared__ u32 s_f[kTreeSlots];     // kF* flags per virtual node
@@ -784,7 +784,9 @@ __global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 r
     build_body(M, count, round, gridDim.x);
 }
 
-constexpr u32 kBarrierSpin = 1u << 20;  // polls before a barrier gives up (~1 s)
+// Polls before a barrier gives up: each poll is an acquire load plus a sleep
+// of 8 x 64 cycles, so the wait lasts at least about 0.2 s.
+constexpr u32 kBarrierSpin = 1u << 20;
 
 // Barrier of the first n workgroups of a grid (all resident): every
 // workgroup releases its writes, counts itself in and waits for the
@@ -919,11 +921,14 @@ __global__ __launch_bounds__(256) void k_alloc(const Member* M, u32 count, u32 v
 // launch.  After the second round a pass rarely has pending roots left (only
 // where one pass splits a region more than kHistLevels levels deep), so the
 // whole grid usually goes straight to the allocation, instead of launches
-// that each find nothing.  When there are, only the first kTailWGs
-// workgroups (at most two per CU by LDS, all resident once the others have
-// exited) run the rounds, separated by barriers among themselves, and then
-// the allocation.  A barrier that times out poisons every member of the pass.
-constexpr u32 kTailWGs = 256;
+// that each find nothing.  When there are, only the first `tail` workgroups
+// run the rounds, separated by barriers among themselves, and then the
+// allocation.  The host sizes `tail` to half of what the device holds of this
+// kernel at once (occupancy x compute units), so the first `tail` workgroups
+// are resident together even beside other work.  A barrier that still times
+// out (the device so shared that they are not) poisons every member of the
+// pass: its later rounds did not run.
+constexpr u32 kTailWGs = 256;  // upper bound of `tail`
 
 __device__ __forceinline__ u32 any_pending(const Member* M, u32 count, u32 round) {
     u32 any = 0u;
@@ -933,7 +938,7 @@ __device__ __forceinline__ u32 any_pending(const Member* M, u32 count, u32 round
 }
 
 __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count, u32 first,
-                                                      u32 last) {
+                                                      u32 last, u32 tail) {
     __shared__ u32 s_any;
     // pending roots from the round before: the same for every workgroup
     // (written before the last barrier or launch, read after it)
@@ -941,7 +946,7 @@ __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count
     __syncthreads();
     const bool rounds = s_any != 0u;  // uniform over the grid
     if (rounds) {
-        if (blockIdx.x >= kTailWGs) return;
+        if (blockIdx.x >= tail) return;
         u32* bar = pass_barrier(M, count);
         for (u32 round = first; round <= last; ++round) {
             if (round > first) {
@@ -949,11 +954,11 @@ __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count
                 __syncthreads();
                 if (!s_any) break;  // uniform
             }
-            count_hist_body(M, count, round, kTailWGs);
-            bool ok = grid_barrier(bar, kTailWGs);
+            count_hist_body(M, count, round, tail);
+            bool ok = grid_barrier(bar, tail);
             if (ok) {
-                build_body(M, count, round, kTailWGs);
-                ok = grid_barrier(bar, kTailWGs);
+                build_body(M, count, round, tail);
+                ok = grid_barrier(bar, tail);
             }
             if (!ok) {
                 if (threadIdx.x < count)
@@ -962,7 +967,7 @@ __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count
             }
         }
     }
-    alloc_body(M, count, 0u, rounds ? kTailWGs : gridDim.x);
+    alloc_body(M, count, 0u, rounds ? tail : gridDim.x);
 }
 
 // ------------------------------------------------------- voxel claim table
@@ -1752,9 +1757,29 @@ hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
     hipLaunchKernelGGL(k_build, dim3(128), dim3(kWG), 0, s, m, count, round);
     return hipGetLastError();
 }
+// Workgroups of the later expansion rounds: half of what the device holds of
+// k_rounds_alloc at once (occupancy per compute unit x compute units), at
+// most kTailWGs and at least 8; queried once per device.
+static u32 tail_workgroups() {
+    static u32 cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64u;
+    if (cached[dev]) return cached[dev];
+    int per_cu = 0, cus = 0;
+    u32 tail = 64u;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rounds_alloc, kWG, 0) ==
+            hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        per_cu > 0 && cus > 0)
+        tail = std::max<u32>(8u, std::min<u32>(kTailWGs, (u32)(per_cu * cus) / 2u) & ~7u);
+    cached[dev] = tail;
+    return tail;
+}
+
 hipError_t launch_rounds_alloc(const Member* m, u32 count, u32 first, u32 last, hipStream_t s) {
-    hipLaunchKernelGGL(k_rounds_alloc, dim3(std::max<u32>(kTailWGs, 1024u)), dim3(kWG), 0, s, m,
-                       count, first, last);
+    const u32 tail = tail_workgroups();
+    hipLaunchKernelGGL(k_rounds_alloc, dim3(std::max<u32>(tail, 1024u)), dim3(kWG), 0, s, m,
+                       count, first, last, tail);
     return hipGetLastError();
 }
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {

@@ -3,23 +3,29 @@ configuration ``bench.py`` times (same capacities, same batch cut).
 
 * aerial (100M points, 1M-point batches): the whole canonical octree equals
   the sequential oracle's, bit for bit.
-* dense scan (1B points, 10M-point batches): too large for one oracle run
-  inside a test, so (i) the whole node table is checked against what the
-  definition fixes at any size (topology from region point totals, voxel
-  counts, chunk totals), and (ii) sampled subtrees are compared bit for bit
-  with the oracle fed only each subtree's region (keys of the whole sequence
-  kept), which by the recursive definition is exactly that subtree.
+* dense scan (1B points, 10M-point batches): every node bit for bit.  The
+  eight depth-1 subtrees are each compared with the sequential oracle fed
+  only that subtree's region (keys of the whole sequence kept; by the
+  recursive definition a subtree depends only on its region's points), the
+  root's voxel list, and again every depth-1 and depth-2 inner node's, with
+  the streamed single-node oracle; the whole node table is also checked
+  against what the definition fixes at any size.
+* batched (64 clouds, 436M points, one group pass per step in the launch
+  shape the benchmark times: autotuned, replayed from a graph): every
+  cloud's whole canonical octree equals its own sequential oracle's.
 """
 
 from __future__ import annotations
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 from oracle import LodConfig, assert_trees_equal
 from oracle.incremental import IncrementalOracle
+from oracle.node_voxels import NodeVoxelOracle
 from tests.gpu_util import log, to_device
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -122,48 +128,141 @@ def _check_node_table(nodes, total, cfg: LodConfig, chunks_in_use: int):
     assert int(((count + C - 1) // C).sum()) == chunks_in_use
 
 
-@pytest.mark.timeout(1200)
-def test_dense_scan_1B_node_table_and_sampled_subtrees():
+def _region_oracle(pts, cfg, path, batch):
+    """The sequential oracle fed the region of node ``path`` (whole-sequence
+    keys), batch by batch as the GPU inserts them."""
+    o = IncrementalOracle(cfg)
+    for i in range(0, len(pts), batch):
+        o.insert_region(pts[i:i + batch], path)
+    return o
+
+
+def _node_oracle(pts, cfg, paths, batch):
+    o = NodeVoxelOracle(cfg, paths)
+    for i in range(0, len(pts), batch):
+        o.feed(pts[i:i + batch])
+    return o
+
+
+@pytest.mark.timeout(1500)
+def test_dense_scan_1B_every_node_bit_exact():
     import bench
 
-    log("case: dense scan 1B, 10M-point batches")
+    log("case: dense scan 1B, 10M-point batches, every node")
     t0 = time.perf_counter()
     pts = bench.generate("dense")
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     tree = _build_on_gpu("dense", pts)
     cfg = _oracle_config("dense")
+    B = bench.WORKLOADS["dense"]["batch"]
     st = tree.stats()
     assert st["status_bits"] == 0 and st["num_points"] == len(pts)
     nodes = tree.snapshot(nodes_only=True).nodes
     log(f"node table: {len(nodes)} nodes, depth {int(nodes['depth'].max())}, "
         f"{st['num_voxels']} voxels")
     _check_node_table(nodes, len(pts), cfg, st["chunks_in_use"])
-
-    # sampled subtrees: a depth-1 octant (the smallest inner one), the
-    # depth-3 ancestor of the deepest node, and the most populated leaf
     path = nodes["path"].astype(np.int64)
     depth = nodes["depth"].astype(np.int64)
     leaf = nodes["is_leaf"] == 1
-    d1 = np.nonzero((depth == 1) & ~leaf)[0]
-    pts_below = {}
-    for i in d1:
-        sub = tree.snapshot(int(path[i]), nodes_only=True).nodes
-        pts_below[int(path[i])] = int(sub["count"][sub["is_leaf"] == 1].sum())
-    octant = min(pts_below, key=pts_below.get)
-    deep = int(path[np.argmax(depth)])
-    deep3 = deep >> (3 * (int(depth.max()) - 3))
-    big_leaf = int(path[leaf][np.argmax(nodes["count"][leaf])])
-    B = bench.WORKLOADS["dense"]["batch"]
-    for p in (deep3, big_leaf, octant):
-        log(f"subtree {p} (depth {(p.bit_length() - 1) // 3})")
-        t0 = time.perf_counter()
-        got = _canonical(tree.snapshot(p))
-        o = IncrementalOracle(cfg)
-        for i in range(0, len(pts), B):
-            o.insert_region(pts[i:i + B], p)
-        want = o.region_subtree(p)
-        o.close()
-        log(f"  {len(got.nodes)} nodes, {len(got.records)} records, "
-            f"{time.perf_counter() - t0:.1f} s")
-        assert_trees_equal(got, want, f"dense subtree {p}")
+    assert not leaf[0], "the root must be inner"
+    d1 = [int(p) for p in path[depth == 1]]
+    d2_inner = {int(p) for p in path[(depth == 2) & ~leaf]}
+    # node oracle groups: the root alone, then each depth-1 inner node with
+    # its depth-2 inner children (one pass over the points per group)
+    groups = [[1]] + [[p] + sorted(c for c in d2_inner if c >> 3 == p)
+                      for p in d1 if not leaf[np.nonzero(path == p)[0][0]]]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=len(d1) + len(groups)) as ex:
+        fut_region = {p: ex.submit(_region_oracle, pts, cfg, p, B) for p in d1}
+        fut_node = [ex.submit(_node_oracle, pts, cfg, g, B) for g in groups]
+        # the inner nodes at depths 0..2, one by one, against the node oracle
+        checked = 0
+        for g, f in zip(groups, fut_node):
+            o = f.result()
+            for p in g:
+                got = tree.snapshot_node(p)
+                want_r, want_k = o.voxels(p)
+                assert got.nodes[0]["is_leaf"] == 0 and got.nodes[0]["count"] == len(want_k)
+                assert np.array_equal(got.keys, want_k), f"voxel keys of node {p}"
+                assert got.records.tobytes() == want_r.tobytes(), f"voxel records of node {p}"
+                checked += 1
+            o.close()
+        log(f"{checked} inner nodes at depths 0..2 equal the node oracle "
+            f"({time.perf_counter() - t0:.1f} s)")
+        # every depth-1 subtree, as each region oracle finishes
+        covered = 1
+        for p in d1:
+            o = fut_region[p].result()
+            want = o.region_subtree(p)
+            o.close()
+            got = _canonical(tree.snapshot(p))
+            assert_trees_equal(got, want, f"dense subtree {p}")
+            covered += len(got.nodes)
+            log(f"  subtree {p}: {len(got.nodes)} nodes, {len(got.records)} records equal "
+                f"({time.perf_counter() - t0:.1f} s)")
+            del got, want
+    assert covered == len(nodes)  # the root plus its eight subtrees: every node
     tree.close()
+
+
+@pytest.mark.timeout(1500)
+def test_batched_64_clouds_every_octree_bit_exact():
+    import torch
+
+    import bench
+    import pointgen
+    from paper_2310_03567_amd import simlod
+
+    log("case: batched, 64 clouds, autotuned group passes replayed from a graph")
+    t0 = time.perf_counter()
+    clouds = pointgen.cloud_set(count=64, seed=3)
+    total = sum(len(c["points"]) for c in clouds)
+    log(f"generated {total} points in {time.perf_counter() - t0:.1f} s")
+    steps = 10
+    devs, cuts = [], []
+    for c in clouds:
+        p = c["points"]
+        devs.append(torch.from_numpy(p.view(np.uint8).reshape(-1)).to("cuda:0"))
+        cuts.append(np.linspace(0, len(p), steps + 1).astype(np.int64))
+    trees = [simlod.Octree(bench.cloud_config(c, int(cuts[i][1] - cuts[i][0]) + 1))
+             for i, c in enumerate(clouds)]
+    group = simlod.Group(trees, graph=True, autotune=True)
+    stream = torch.cuda.current_stream()
+
+    def run_steps():
+        for k in range(steps):
+            group.insert([d[int(c[k]) * 16:int(c[k + 1]) * 16] for d, c in zip(devs, cuts)],
+                         stream)
+
+    run_steps()  # tuning passes
+    for t in trees:
+        t.reset(stream)
+    run_steps()  # the tuned shape, replayed from the captured graph
+    group.sync()
+    shape = group.shape()
+    assert shape["tuned"] and shape["graph"], shape
+    group.close()
+    del devs
+    torch.cuda.empty_cache()
+
+    def oracle_of(i):
+        c = clouds[i]
+        o = IncrementalOracle(LodConfig(root_min=c["root_min"], root_size=c["root_size"]))
+        p = c["points"]
+        for k in range(steps):
+            o.insert(p[int(cuts[i][k]):int(cuts[i][k + 1])])
+        want = o.canonical()
+        o.close()
+        return want
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        futs = [ex.submit(oracle_of, i) for i in range(len(clouds))]
+        for i, f in enumerate(futs):
+            want = f.result()
+            st = trees[i].stats()
+            assert st["status_bits"] == 0 and st["num_points"] == len(clouds[i]["points"])
+            assert_trees_equal(_canonical(trees[i].snapshot()), want, f"cloud {i}")
+    log(f"64 octrees equal their oracles ({time.perf_counter() - t0:.1f} s)")
+    for t in trees:
+        t.close()

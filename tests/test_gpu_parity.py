@@ -253,3 +253,57 @@ def test_chunk_list_reader_equals_table_export(C):
     assert a.records.tobytes() == b.records.tobytes()
     assert np.array_equal(a.keys, b.keys)
     assert_trees_equal(canonical_of(b), O1.build(p, cfg))
+
+
+def test_alternating_streams_keep_call_order():
+    """Calls on one handle made on different streams run in call order: the
+    library makes each new stream wait for the handle's earlier work (the
+    passes share the octree's counters, claim table and spill buffers)."""
+    import torch
+
+    import pointgen
+
+    p = pointgen.tiny_planes(400_000, seed=31)
+    cfg = LodConfig(leaf_capacity=2_000, grid_bits=5, max_depth=10, chunk_capacity=250)
+    log("case: alternating torch streams, 16 batches, then a reset on a third stream")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev = to_device(p)
+    torch.cuda.synchronize()
+    with make_octree(cfg, arena_bytes=1 << 30) as tree:
+        for k in range(16):
+            a, b = k * 25_000, (k + 1) * 25_000
+            tree.insert(dev[a * 16:b * 16], streams[k % 2])
+        assert_trees_equal(canonical(tree), O1.build(p, cfg), "alternating streams")
+        third = torch.cuda.Stream()
+        tree.reset(third)
+        tree.insert(dev[:150_000 * 16], streams[0])
+        tree.insert(dev[150_000 * 16:300_000 * 16], third)
+        assert_trees_equal(canonical(tree), O1.build(p[:300_000], cfg), "after reset")
+
+
+def test_single_node_export_equals_its_slice_of_the_whole():
+    import pointgen
+    from oracle import subtree
+    from paper_2310_03567_amd import simlod
+
+    p = pointgen.tiny_planes(200_000, seed=33)
+    cfg = LodConfig(leaf_capacity=3_000, grid_bits=5, max_depth=9, chunk_capacity=300)
+    log("case: single-node exports")
+    with make_octree(cfg, arena_bytes=1 << 30) as tree:
+        insert_batches(tree, to_device(p), [60_000, 140_000])
+        whole = canonical(tree)
+        for i in list(range(min(40, len(whole.nodes)))):
+            path = int(whole.nodes["path"][i])
+            s = tree.snapshot_node(path)
+            assert len(s.nodes) == 1
+            want = subtree(whole, path)
+            n0 = want.nodes[0]
+            assert (s.nodes[0]["path"], s.nodes[0]["count"], s.nodes[0]["depth"],
+                    s.nodes[0]["is_leaf"], s.nodes[0]["first"]) == (
+                n0["path"], n0["count"], n0["depth"], n0["is_leaf"], 0)
+            r, k = want.node_records(0)
+            assert s.records.tobytes() == r.tobytes() and np.array_equal(s.keys, k)
+        leaf = int(whole.nodes["path"][np.nonzero(whole.nodes["is_leaf"] == 1)[0][0]])
+        with pytest.raises(simlod.SimlodError) as e:
+            tree.snapshot_node(leaf * 8 + 3)
+        assert e.value.code == simlod.ERR_NOT_FOUND

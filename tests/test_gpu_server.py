@@ -50,13 +50,27 @@ def _simlod_cfg(cfg: LodConfig, max_batch):
                               spill_capacity=1 << 19, backlog_capacity=1 << 19)
 
 
-def _serve(streams, max_per_pass, seed):
+def _serve(streams, max_per_pass, seed, where=None, staging=0):
+    """where[k]: "device" (default), "pinned" or "pageable" host memory for
+    stream k's requests."""
+    import torch
+
     from paper_2310_03567_amd import simlod
 
-    with simlod.Server(max_streams=8, hbm_budget=64 << 30, max_per_pass=max_per_pass) as sv:
+    where = where or ["device"] * len(streams)
+    with simlod.Server(max_streams=8, hbm_budget=64 << 30, max_per_pass=max_per_pass,
+                       staging_bytes=staging) as sv:
         ids = [sv.open(_simlod_cfg(cfg, 40_000)) for cfg, _ in streams]
         assert None not in ids
-        devs = [to_device(p) for _, p in streams]
+        devs = []
+        for (_, p), w in zip(streams, where):
+            raw = np.ascontiguousarray(p).view(np.uint8).reshape(-1)
+            if w == "device":
+                devs.append(to_device(p))
+            elif w == "pinned":
+                devs.append(torch.from_numpy(raw).pin_memory().numpy())
+            else:
+                devs.append(raw.copy())
         tickets = [[] for _ in streams]
         errors = []
 
@@ -195,3 +209,45 @@ def test_pooled_octree_reused_with_another_configuration():
         s = sv.octree(b).snapshot()
         assert_trees_equal(CanonicalTree(nodes=s.nodes, records=s.records, keys=s.keys),
                            O1.build(q, small))
+
+
+def test_served_host_memory_streams_equal_their_oracle():
+    """Requests in pinned and pageable host memory go through the server's
+    uploader (copies into a small staging area, so uploads wait for space
+    that completed passes free) mixed with device requests; every stream's
+    octree is exactly its oracle's."""
+    rng = np.random.default_rng(37)
+    streams = []
+    for k in range(6):
+        cfg = LodConfig(leaf_capacity=int(rng.choice([20, 50, 500])),
+                        grid_bits=int(rng.integers(1, 5)), max_depth=int(rng.integers(4, 10)),
+                        chunk_capacity=int(rng.choice([3, 64, 1000])))
+        streams.append((cfg, _cloud(rng, int(rng.integers(20_000, 120_000)))))
+    where = ["pinned", "pageable", "device", "pinned", "pageable", "device"]
+    log("case: served from host memory, 6 streams, 2 MiB staging")
+    for max_per_pass in (0, 1):
+        got, lat, counters = _serve(streams, max_per_pass, seed=38, where=where,
+                                    staging=2 << 20)
+        for k, ((cfg, p), t) in enumerate(zip(streams, got)):
+            assert_trees_equal(t, O1.build(p, cfg), f"stream {k} ({where[k]}) n={len(p)}")
+        assert counters["points"] == sum(len(p) for _, p in streams)
+
+
+def test_host_request_needs_staging_and_fits_it():
+    from paper_2310_03567_amd import simlod
+
+    cfg = _simlod_cfg(LodConfig(leaf_capacity=50, grid_bits=3, max_depth=8), 100_000)
+    p = _cloud(np.random.default_rng(39), 70_000)
+    with simlod.Server(max_streams=2, hbm_budget=64 << 30) as sv:
+        a = sv.open(cfg)
+        with pytest.raises(simlod.SimlodError) as e:
+            sv.submit(a, p)  # host memory, no staging
+        assert e.value.code == simlod.ERR_INVALID_ARGUMENT
+    with simlod.Server(max_streams=2, hbm_budget=64 << 30, staging_bytes=1 << 20) as sv:
+        a = sv.open(cfg)
+        with pytest.raises(simlod.SimlodError) as e:
+            sv.submit(a, p)  # 1.1 MB > 1 MiB of staging
+        assert e.value.code == simlod.ERR_INVALID_ARGUMENT
+        t = sv.submit(a, p[:60_000])
+        sv.drain()
+        assert sv.poll(t)[2] == simlod.OK

@@ -1,0 +1,98 @@
+"""simlod_insert_batch_static, the entry point for callers that cannot
+allocate device memory: host input staged through the library's static
+device array.  Its octree must equal simlod_insert_batch's, bit for bit, on
+two calls in a row (the second smaller, so stale staged points must not
+leak in), and sizes beyond the array are rejected."""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import POINT_DTYPE, LodConfig, assert_trees_equal
+from oracle import definition as O1
+from tests.gpu_util import canonical, log, make_octree, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_03567_amd import simlod  # noqa: F401  (fails loudly if not built)
+
+
+def _cloud(rng, n):
+    xyz = rng.random((n, 3)) ** 2
+    p = np.zeros(n, dtype=POINT_DTYPE)
+    p["x"], p["y"], p["z"] = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    p["rgba"] = rng.integers(0, 2**32, n, dtype=np.uint32)
+    return p
+
+
+def test_static_staging_equals_allocating_insert_on_two_calls():
+    log("case: insert_batch_static vs insert_batch, host input, 300k then 70k points")
+    rng = np.random.default_rng(71)
+    cfg = LodConfig(leaf_capacity=3000, grid_bits=5, max_depth=10, chunk_capacity=256)
+    pts = _cloud(rng, 370_000)
+    a = make_octree(cfg, max_batch=1 << 17)  # calls cut into several passes
+    b = make_octree(cfg, max_batch=1 << 17)
+    try:
+        for lo, hi in ((0, 300_000), (300_000, 370_000)):
+            a.insert(pts[lo:hi])          # allocating staging
+            b.insert_static(pts[lo:hi])   # static staging
+            ga, gb = canonical(a), canonical(b)
+            assert_trees_equal(gb, ga, f"static vs allocating after {hi} points")
+        assert_trees_equal(canonical(b), O1.build(pts, cfg), "static vs definition")
+    finally:
+        a.close()
+        b.close()
+
+
+def test_static_staging_interleaved_handles_and_device_input():
+    from paper_2310_03567_amd import simlod
+
+    log("case: two handles alternating static calls on two streams, then device input")
+    import torch
+
+    rng = np.random.default_rng(72)
+    cfg = LodConfig(leaf_capacity=500, grid_bits=4, max_depth=8, chunk_capacity=100)
+    p1, p2 = _cloud(rng, 120_000), _cloud(rng, 90_000)
+    t1, t2 = make_octree(cfg), make_octree(cfg)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        for k in range(3):
+            t1.insert_static(p1[k * 40_000:(k + 1) * 40_000], s1)
+            t2.insert_static(p2[k * 30_000:(k + 1) * 30_000], s2)
+        assert_trees_equal(canonical(t1), O1.build(p1, cfg), "handle 1")
+        assert_trees_equal(canonical(t2), O1.build(p2, cfg), "handle 2")
+        extra = _cloud(rng, 5_000)
+        t1.insert_static(to_device(extra))
+        assert_trees_equal(canonical(t1), O1.build(np.concatenate([p1, extra]), cfg),
+                           "device input")
+    finally:
+        t1.close()
+        t2.close()
+
+
+def test_static_staging_rejects_more_than_its_array():
+    from paper_2310_03567_amd import simlod
+
+    cfg = LodConfig(leaf_capacity=50_000, grid_bits=7, max_depth=16)
+    t = make_octree(cfg, max_batch=1 << 21, spill_capacity=1 << 21, backlog_capacity=1 << 21)
+    try:
+        big = np.zeros((1 << 20) + 1, dtype=POINT_DTYPE)
+        with pytest.raises(simlod.SimlodError) as ei:
+            t.insert_static(big)
+        assert ei.value.code == simlod.ERR_INVALID_ARGUMENT
+        assert b"static staging buffer" in simlod.lib.simlod_last_error()
+        assert t.stats()["points_inserted"] == 0  # nothing was enqueued
+        t.insert_static(big[: 1 << 20])  # exactly the limit is accepted
+        assert t.stats()["points_inserted"] == 1 << 20
+    finally:
+        t.close()
