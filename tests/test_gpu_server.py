@@ -40,17 +40,17 @@ def _cloud(rng, n):
     return p
 
 
-def _simlod_cfg(cfg: LodConfig, max_batch):
+def _simlod_cfg(cfg: LodConfig, max_batch, arena_bytes=256 << 20):
     from paper_2310_03567_amd import simlod
 
     return simlod.make_config(root_min=cfg.root_min, root_size=cfg.root_size,
                               leaf_capacity=cfg.leaf_capacity, grid_bits=cfg.grid_bits,
                               max_depth=cfg.max_depth, chunk_capacity=cfg.chunk_capacity,
-                              max_nodes=1 << 17, arena_bytes=256 << 20, max_batch=max_batch,
+                              max_nodes=1 << 17, arena_bytes=arena_bytes, max_batch=max_batch,
                               spill_capacity=1 << 19, backlog_capacity=1 << 19)
 
 
-def _serve(streams, max_per_pass, seed, where=None, staging=0):
+def _serve(streams, max_per_pass, seed, where=None, staging=0, arena_bytes=256 << 20):
     """where[k]: "device" (default), "pinned" or "pageable" host memory for
     stream k's requests."""
     import torch
@@ -60,7 +60,7 @@ def _serve(streams, max_per_pass, seed, where=None, staging=0):
     where = where or ["device"] * len(streams)
     with simlod.Server(max_streams=8, hbm_budget=64 << 30, max_per_pass=max_per_pass,
                        staging_bytes=staging) as sv:
-        ids = [sv.open(_simlod_cfg(cfg, 40_000)) for cfg, _ in streams]
+        ids = [sv.open(_simlod_cfg(cfg, 40_000, arena_bytes)) for cfg, _ in streams]
         assert None not in ids
         devs = []
         for (_, p), w in zip(streams, where):
@@ -225,9 +225,11 @@ def test_served_host_memory_streams_equal_their_oracle():
         streams.append((cfg, _cloud(rng, int(rng.integers(20_000, 120_000)))))
     where = ["pinned", "pageable", "device", "pinned", "pageable", "device"]
     log("case: served from host memory, 6 streams, 2 MiB staging")
+    # stream 2 (T = 20, chunks of 1,000, 118,587 points) keeps about 23k
+    # chunks of 20 KB: 470 MB of persistent buffer, so each stream gets 1 GiB
     for max_per_pass in (0, 1):
         got, lat, counters = _serve(streams, max_per_pass, seed=38, where=where,
-                                    staging=2 << 20)
+                                    staging=2 << 20, arena_bytes=1 << 30)
         for k, ((cfg, p), t) in enumerate(zip(streams, got)):
             assert_trees_equal(t, O1.build(p, cfg), f"stream {k} ({where[k]}) n={len(p)}")
         assert counters["points"] == sum(len(p) for _, p in streams)
