@@ -1021,6 +1021,11 @@ constexpr u32 kNodeBits = 8;     // inner nodes with new voxels per workgroup
 
 constexpr u32 kCandBits = 10;  // claim candidates per tile, deduplicated in LDS
 constexpr u32 kCands = 1u << kCandBits;
+// Candidates the tile's table has no entry for (an overfull table: scans
+// where every point meets fresh cells on many levels) wait in an overflow
+// list and are claimed in the same round trip as the table's entries; only
+// beyond kOvf per tile is a candidate claimed at once.
+constexpr u32 kOvf = 256;
 
 // Stages a claim the calling lane created: the claim-table slot goes to the
 // workgroup's LDS buffer (straight to the stripe when that is full) and the
@@ -1061,10 +1066,10 @@ __device__ __forceinline__ void stage_claim(const DevTree& t, u32 hslot, u32 nod
 // may be overwritten by a new live entry.  Returns false when no entry was
 // found within the probe limit.
 constexpr u64 kSubmitted = 1ull << 63;  // tags use bits 0..55
-// Probes of a candidate insert before the candidate is claimed globally at
-// once: in an overfull table (dense scans) long probe chains of atomics cost
-// more than the claim they save.
-constexpr u32 kCandProbe = 16;
+// Probes of a candidate insert before the candidate goes to the overflow
+// list: in an overfull table (dense scans) long probe chains of LDS atomics
+// cost more than the global claim they save.
+constexpr u32 kCandProbe = 2;
 
 // Home entry of a cell in the LDS candidate table: a 32-bit multiplicative
 // hash of (node, cell), cheaper than a 64-bit mix; any spread will do, the
@@ -1126,12 +1131,14 @@ __device__ __forceinline__ void claim_now(const DevTree& t, u64 tag, u32 key, u6
 // inner tests its cell's bit (word = the grid word holding it, loaded by the
 // caller); a clear bit makes the cell a candidate.  Consecutive lanes on the
 // same cell with increasing keys add it once; candidates are merged in the
-// tile's LDS table (smallest key per cell) and claimed globally, all at once,
-// after the traversal.  Must be reached by the whole wave.
+// tile's LDS table (smallest key per cell), or else listed in the overflow
+// list, and claimed globally, all at once, after the traversal.  Must be
+// reached by the whole wave.
 __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
                                                  u32 rgba, bool batch_item, u32 lane, u64* ctag,
                                                  u64* cval, u16* s_live, u32* s_nlive,
+                                                 u64* s_ovf, u32* s_novf,
                                                  u32 stripe, u32 base_key,
                                                  u32* s_claims, u32* s_nclaims, u32* s_vkey,
                                                  u32* s_vcnt, u32* s_vfill) {
@@ -1145,29 +1152,49 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
-    if (cand && !cand_insert(ctag, cval, s_live, s_nlive, tag, val, batch_item))  // no entry: claim now
-        claim_now(t, tag, key, val, stripe, base_key, s_claims, s_nclaims, s_vkey, s_vcnt,
-                  s_vfill);
+    if (cand && !cand_insert(ctag, cval, s_live, s_nlive, tag, val, batch_item)) {
+        const u32 o = atomicAdd(s_novf, 1u);
+        if (o < kOvf) {  // claimed with the table's entries
+            s_ovf[2u * o] = tag;
+            s_ovf[2u * o + 1u] = val;
+        } else {  // overflow list full too: claim now
+            claim_now(t, tag, key, val, stripe, base_key, s_claims, s_nclaims, s_vkey, s_vcnt,
+                      s_vfill);
+        }
+    }
 }
 
 // Claims of one tile, in two halves so that other global atomics can share
 // the round trip: claim_issue takes a thread's entries of the LDS candidate
-// table and issues a CAS of each one's claim word into its home entry;
-// claim_resolve handles what the CAS found (an entry created, the cell's
-// entry holding a larger key, another cell's entry: probe on) and stages the
-// claims this workgroup created.
+// table (and of the overflow list) and loads each one's home entry of the
+// claim table with a plain load; claim_resolve then drops the candidates
+// whose cell is already claimed with a smaller key, issues a CAS where the
+// entry was empty, and handles what that found (an entry created, the
+// cell's entry holding a larger key: atomic min, another cell's entry:
+// probe on), and stages the claims this workgroup created.
+//
+// The plain load may return a stale copy of the entry, but within a pass an
+// entry only goes from empty to one cell's claim word, whose key only
+// decreases: a stale copy shows an empty entry (the CAS then finds the
+// truth) or a key at least the current one, so a candidate it shows as
+// dominated is dominated.  In a dense scan most candidates meet a cell
+// another workgroup claimed earlier in the pass; the load answers them
+// without a device-scope atomic (which is performed past the L2 and
+// writes a whole line).
 constexpr u32 kCandPer = kCands / 256u;
+constexpr u32 kClaimPer = kCandPer + kOvf / 256u;  // + the overflow list's
+static_assert(kOvf % 256u == 0u, "overflow entries are dealt one per thread and slot");
 struct ClaimBatch {
-    u64 tg[kCandPer], vl[kCandPer], cur[kCandPer];
-    u32 hh[kCandPer], rm[kCandPer];
+    u64 tg[kClaimPer], vl[kClaimPer], cur[kClaimPer];
+    u32 hh[kClaimPer], rm[kClaimPer];
 };
 
 // keep: the workgroup's next tile belongs to the same octree, so submitted
 // cells stay in the table as dominance markers; otherwise it starts empty.
 // Whole workgroup, after a barrier that follows the tile's inserts.
 __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cval,
-                                            const u16* s_live, u32 nlive, ClaimBatch& b,
-                                            bool keep) {
+                                            const u16* s_live, u32 nlive, const u64* s_ovf,
+                                            u32 novf, ClaimBatch& b, bool keep) {
 #pragma unroll
     for (u32 k = 0; k < kCandPer; ++k) {
         const u32 i = threadIdx.x + k * 256u;
@@ -1183,6 +1210,18 @@ __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cv
             claim_home(t, cell_identity(t, b.tg[k]), b.hh[k], b.rm[k]);
         }
     }
+#pragma unroll
+    for (u32 k = kCandPer; k < kClaimPer; ++k) {  // the overflow list
+        const u32 i = threadIdx.x + (k - kCandPer) * 256u;
+        b.tg[k] = kEmptyTag;
+        b.vl[k] = ~0ull;
+        b.hh[k] = b.rm[k] = 0u;
+        if (i < min(novf, kOvf)) {
+            b.tg[k] = s_ovf[2u * i];
+            b.vl[k] = s_ovf[2u * i + 1u];
+            claim_home(t, cell_identity(t, b.tg[k]), b.hh[k], b.rm[k]);
+        }
+    }
     if (!keep) {  // uniform: every entry, markers included, cleared
         __syncthreads();
         for (u32 i = threadIdx.x; i < kCands; i += kWG) {
@@ -1191,29 +1230,34 @@ __device__ __forceinline__ void claim_issue(const DevTree& t, u64* ctag, u64* cv
         }
     }
 #pragma unroll
-    for (u32 k = 0; k < kCandPer; ++k)
-        b.cur[k] = b.tg[k] != kEmptyTag
-                       ? atomicCAS((unsigned long long*)claim_word_at(t, b.hh[k]),
-                                   (unsigned long long)kEmptyWord,
-                                   (unsigned long long)(((u64)(b.rm[k] << kDistBits) << 32) |
-                                                        (b.vl[k] >> 32)))
-                       : 0ull;
+    for (u32 k = 0; k < kClaimPer; ++k)
+        b.cur[k] = b.tg[k] != kEmptyTag ? *claim_word_at(t, b.hh[k]) : 0ull;
 }
 
 __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch& b, u32 stripe,
                                               u32 base_key, u32* s_claims, u32* s_nclaims,
                                               u32* s_vkey, u32* s_vcnt, u32* s_vfill) {
+    u64 cur[kClaimPer];
 #pragma unroll
-    for (u32 k = 0; k < kCandPer; ++k) {
+    for (u32 k = 0; k < kClaimPer; ++k)
+        cur[k] = (b.tg[k] != kEmptyTag && b.cur[k] == kEmptyWord)
+                     ? atomicCAS((unsigned long long*)claim_word_at(t, b.hh[k]),
+                                 (unsigned long long)kEmptyWord,
+                                 (unsigned long long)(((u64)(b.rm[k] << kDistBits) << 32) |
+                                                      (b.vl[k] >> 32)))
+                     : b.cur[k];
+#pragma unroll
+    for (u32 k = 0; k < kClaimPer; ++k) {
         if (b.tg[k] == kEmptyTag) continue;
         const u32 key = (u32)(b.vl[k] >> 32);
         const u32 tg0 = b.rm[k] << kDistBits;
         bool fresh = false, found = true;
         u32 slot = b.hh[k];
-        if (b.cur[k] == kEmptyWord) {
+        if ((u32)(cur[k] >> 32) == tg0 && (u32)cur[k] <= key) continue;  // dominated
+        if (cur[k] == kEmptyWord) {
             fresh = true;
-        } else if ((u32)(b.cur[k] >> 32) == tg0) {
-            if ((u32)b.cur[k] > key)
+        } else if ((u32)(cur[k] >> 32) == tg0) {
+            if ((u32)cur[k] > key)
                 atomicMin((unsigned long long*)claim_word_at(t, slot),
                           (unsigned long long)(((u64)tg0 << 32) | key));
         } else {  // another cell's entry: probe on
@@ -1227,7 +1271,7 @@ __device__ __forceinline__ void claim_resolve(const DevTree& t, const ClaimBatch
     }
 }
 
-constexpr u32 kClaimFlushAt = kClaimBuf - kCands - kWG;  // room for one more tile
+constexpr u32 kClaimFlushAt = kClaimBuf - kCands - kOvf - kWG;  // room for one more tile
 constexpr u32 kNodeFlushAt = (1u << kNodeBits) / 2u;
 
 // Appends the workgroup's staged claims to its stripe's list (one atomic)
@@ -1289,7 +1333,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
     __shared__ u64 s_ctag[kCands], s_cval[kCands];
     __shared__ u16 s_live[kCands];  // live entries of the tile's candidate table
-    __shared__ u32 s_nclaims, s_flush, s_vfill, s_nlive;
+    __shared__ u64 s_ovf[2u * kOvf];  // overflow list: (tag, value) pairs
+    __shared__ u32 s_nclaims, s_flush, s_vfill, s_nlive, s_novf;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     const u32 nwg = gridDim.x;
@@ -1309,6 +1354,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         s_nclaims = 0u;
         s_vfill = 0u;
         s_nlive = 0u;
+        s_novf = 0u;
     }
     const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
         const Counters* ctr = M[c].tree->ctr;
@@ -1369,7 +1415,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
                 desc = false;
             }
             level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w,
-                             batch_item, lane, s_ctag, s_cval, s_live, &s_nlive, stripe,
+                             batch_item, lane, s_ctag, s_cval, s_live, &s_nlive, s_ovf,
+                             &s_novf, stripe,
                              base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         }
         // Below the directory: dependent walk through child[].
@@ -1386,7 +1433,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
             level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, batch_item, lane,
-                             s_ctag, s_cval, s_live, &s_nlive, stripe, base_key, s_claims,
+                             s_ctag, s_cval, s_live, &s_nlive, s_ovf, &s_novf, stripe,
+                             base_key, s_claims,
                              &s_nclaims, s_vkey, s_vcnt, &s_vfill);
             if (inner) node = ch + octant_of(qx, qy, qz, t.K - 1u - d);
         }
@@ -1411,7 +1459,7 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         // one round trip for the tile: claim CASes, one slot reservation per
         // leaf, and the next tile's records
         ClaimBatch cb;
-        claim_issue(t, s_ctag, s_cval, s_live, s_nlive, cb, cn == c);
+        claim_issue(t, s_ctag, s_cval, s_live, s_nlive, s_ovf, s_novf, cb, cn == c);
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
@@ -1421,7 +1469,10 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         if (nx != kNone) fetch(cn, nx, rec_n, key_n);
         claim_resolve(t, cb, stripe, base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
         __syncthreads();
-        if (tid == 0) s_nlive = 0u;  // every thread read it in claim_issue, before the barrier
+        if (tid == 0) {  // every thread read them in claim_issue, before the barrier
+            s_nlive = 0u;
+            s_novf = 0u;
+        }
         if (valid) {
             const u32 slot = s_lbase[le] + r0;
             const u32 ci = div_C(t, slot);
