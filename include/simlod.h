@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define SIMLOD_ABI_VERSION 1
+#define SIMLOD_ABI_VERSION 2
 
 /* ---- status codes ---------------------------------------------------- */
 #define SIMLOD_OK 0
@@ -124,6 +124,16 @@ typedef struct simlod_point {
  * backlog_capacity     New voxels in one pass (section "Voxel Sampling"
  *                      suggests 10M).
  * device               HIP device ordinal.
+ * arena_ptr            Caller-owned persistent buffer, or NULL (the library
+ *                      allocates it).  Device memory of at least arena_bytes
+ *                      (> 0) on `device`, 256-byte aligned, owned by the
+ *                      caller (for instance a torch tensor), which must keep
+ *                      it alive and untouched until simlod_destroy; the
+ *                      library zeroes it at creation and never frees it.  The
+ *                      paper's persistent buffer is one allocation made up
+ *                      front (section "Persistent Buffer"); this lets the
+ *                      caller's allocator make it.  Not accepted by the
+ *                      server, which owns the memory of its octrees.
  */
 typedef struct simlod_config {
     float root_min[3];
@@ -140,6 +150,7 @@ typedef struct simlod_config {
     uint64_t backlog_capacity;
     int32_t device;
     uint32_t reserved1;
+    void* arena_ptr;
 } simlod_config;
 
 /* Node record of the canonical export: preorder, children in octant order
@@ -423,7 +434,8 @@ typedef struct simlod_server_config {
 
 int simlod_server_create(const simlod_server_config* cfg, simlod_server** out);
 
-/* Device bytes simlod_create allocates for *cfg (arena_bytes must be set:
+/* Device bytes simlod_create allocates for *cfg, a caller-owned arena_ptr
+ * buffer not included (arena_bytes must be set:
  * a served octree cannot take "90% of free memory"). */
 int simlod_config_device_bytes(const simlod_config* cfg, uint64_t* bytes);
 

@@ -155,6 +155,10 @@ bool cfg_valid(const simlod_config* c) {
         return false;
     if (c->backlog_capacity < 1 || c->backlog_capacity > (1ull << 31)) return false;
     if (c->hist_capacity > (1u << 31) / kHistEntries) return false;
+    // a caller-owned persistent buffer: a size, and block alignment
+    if (c->arena_ptr && (c->arena_bytes < kBlockBytes ||
+                         reinterpret_cast<uintptr_t>(c->arena_ptr) % kBlockBytes))
+        return false;
     return true;
 }
 
@@ -481,9 +485,25 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
     u64 blocks = std::min<u64>(arena_bytes / kBlockBytes, 0xFFFFFFF0ull);
     t.arena_blocks = (u32)blocks;
     t.pool_cap = t.arena_blocks / t.chunk_blocks + 1;
-    ok = ok && blocks > 0 && dalloc(h, &t.arena, blocks * (u64)kBlockBytes) &&
-         dalloc(h, &t.pool, t.pool_cap);
+    if (cfg->arena_ptr) {  // the caller's buffer: used, never freed
+        if (!h->dry) t.arena = (GPtr<uint8_t>)cfg->arena_ptr;
+        ok = ok && blocks > 0 && dalloc(h, &t.pool, t.pool_cap);
+    } else {
+        ok = ok && blocks > 0 && dalloc(h, &t.arena, blocks * (u64)kBlockBytes) &&
+             dalloc(h, &t.pool, t.pool_cap);
+    }
     return ok;
+}
+
+// A caller-owned persistent buffer must be device memory of `device`.
+static bool arena_ptr_ok(const void* p, int device) {
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice && attr.device == device;
 }
 
 extern "C" {
@@ -519,6 +539,11 @@ int simlod_create(const simlod_config* cfg, simlod_octree** out) {
     }
     if (cfg->device < 0 || cfg->device >= ndev) return SIMLOD_ERR_INVALID_ARGUMENT;
     DeviceGuard guard(cfg->device);
+    if (cfg->arena_ptr && !arena_ptr_ok(cfg->arena_ptr, cfg->device)) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "arena_ptr is not device memory of device %d", cfg->device);
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
     simlod_octree* h = new (std::nothrow) simlod_octree();
     if (!h) return SIMLOD_ERR_OUT_OF_MEMORY;
     h->cfg = *cfg;
@@ -1873,6 +1898,11 @@ int simlod_server_create(const simlod_server_config* cfg, simlod_server** out) {
 
 int simlod_server_open(simlod_server* sv, const simlod_config* cfg, uint32_t* id) {
     if (!sv || !cfg || !id || cfg->device != sv->cfg.device) return SIMLOD_ERR_INVALID_ARGUMENT;
+    if (cfg->arena_ptr) {  // the server owns (and pools) its octrees' memory
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "simlod_server_open: arena_ptr must be NULL");
+        return SIMLOD_ERR_INVALID_ARGUMENT;
+    }
     u64 bytes = 0;
     int rc = simlod_config_device_bytes(cfg, &bytes);
     if (rc) return rc;

@@ -63,6 +63,7 @@ class Config(ctypes.Structure):
         ("backlog_capacity", ctypes.c_uint64),
         ("device", ctypes.c_int32),
         ("reserved1", ctypes.c_uint32),
+        ("arena_ptr", ctypes.c_void_p),
     ]
 
 
@@ -343,8 +344,15 @@ class Snapshot:
 class Octree:
     """Owning wrapper around one handle."""
 
-    def __init__(self, cfg: Config | None = None, **kw):
-        self.cfg = cfg if cfg is not None else make_config(**kw)
+    def __init__(self, cfg: Config | None = None, arena=None, **kw):
+        """arena: optional caller-owned persistent buffer, a device tensor
+        (256-byte aligned); held here until close()."""
+        self.cfg = Config.from_buffer_copy(cfg) if cfg is not None else make_config(**kw)
+        self._arena = None
+        if arena is not None:
+            self.cfg.arena_ptr = arena.data_ptr()
+            self.cfg.arena_bytes = arena.numel() * arena.element_size()
+            self._arena = arena
         self.handle = create(self.cfg)
 
     def insert(self, points, stream=None) -> None:
@@ -371,9 +379,10 @@ class Octree:
         reset(self.handle, stream)
 
     def close(self) -> None:
-        if self.handle:
+        if getattr(self, "handle", None):
             destroy(self.handle)
             self.handle = None
+        self._arena = None
 
     def __enter__(self):
         return self
