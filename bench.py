@@ -227,7 +227,13 @@ def run_served(args):
     last request) and the slot admits the next cloud against a 200 GB
     device-memory budget.  The same arrival trace is served twice: batched
     (every pass takes the oldest request of each stream) and unbatched (one
-    request per pass, arrival order).  Latency = submission to completion."""
+    request per pass, arrival order).  Latency = submission to completion.
+
+    Offered loads: unless --offered names them, 0.5, 0.8 and 0.95 of the
+    capacity of the unbatched form, measured first with every request
+    arriving at once.  Throughput is reported over the wall time of a run and
+    over its busy time (the union of the intervals in which at least one
+    request was outstanding), which the arrival trace does not stretch."""
     import torch
 
     import pointgen
@@ -256,6 +262,7 @@ def run_served(args):
         rate = offered_pps / slots / mean_req  # requests/s per slot
         rng = np.random.default_rng(seed)
         lat = []
+        spans = []  # (submission, completion) of every request, seconds
         c0 = sv.counters()
         queue = list(range(len(clouds)))
         active = {}  # slot index -> [cloud, next request, stream id, next arrival, tickets]
@@ -279,16 +286,17 @@ def run_served(args):
                 cuts = reqs[ci]
                 while r < len(cuts) - 1 and t_next <= now:
                     b = devs[ci][cuts[r] * 16:cuts[r + 1] * 16]
-                    tickets.append(sv.submit(sid, b))
+                    tickets.append((sv.submit(sid, b), time.perf_counter() - start))
                     r += 1
                     t_next += rng.exponential(1.0 / rate)
                 st[1], st[3] = r, t_next
-                if r == len(cuts) - 1 and all(sv.poll(t)[0] for t in tickets[-1:]):
-                    for t in tickets:
+                if r == len(cuts) - 1 and all(sv.poll(t)[0] for t, _ in tickets[-1:]):
+                    for t, ts in tickets:
                         d, ms, rc = sv.poll(t)
                         if not d or rc != simlod.OK:
                             raise RuntimeError(f"request failed ({rc})")
                         lat.append(ms)
+                        spans.append((ts, ts + ms / 1e3))
                     done_points += cuts[-1]
                     sv.close_stream(sid)
                     active[k] = None
@@ -300,29 +308,48 @@ def run_served(args):
         c = sv.counters()
         lat = np.array(lat)
         passes = int(c["passes"] - c0["passes"])
+        busy, end = 0.0, -1.0  # union of the outstanding intervals
+        for a, b in sorted(spans):
+            if b > end:
+                busy += b - max(a, end)
+                end = b
         return {"offered_points_per_s": round(offered_pps, 1),
                 "achieved_points_per_s": round(done_points / el, 1),
+                "busy_points_per_s": round(done_points / max(busy, 1e-9), 1),
+                "busy_seconds": round(busy, 3),
                 "requests": int(len(lat)), "passes": passes,
                 "requests_per_pass": round(len(lat) / max(passes, 1), 2),
                 "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                 "seconds": round(el, 3)}
 
-    loads = [float(x) * 1e9 for x in str(args.offered).split(",")]
-    runs = {}
-    for form, per_pass in (("batched", 0), ("unbatched", 1)):
-        # one server per form; its warm-up run allocates the octrees, which
-        # the timed runs then reuse from the server's pool
-        sv = simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=per_pass)
-        serve(sv, loads[0], seed=40)
-        runs[form] = [serve(sv, offered, seed=41 + k) for k, offered in enumerate(loads)]
+    # one server per form; a warm-up run allocates the octrees, which the
+    # measured runs then reuse from the server's pool
+    servers = {form: simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=per_pass)
+               for form, per_pass in (("batched", 0), ("unbatched", 1))}
+    capacity = None
+    if args.offered:
+        loads = [float(x) * 1e9 for x in str(args.offered).split(",")]
+        for sv in servers.values():
+            serve(sv, loads[0], seed=40)
+    else:
+        for sv in servers.values():
+            serve(sv, 1e13, seed=40)  # warm-up
+        cap_run = serve(servers["unbatched"], 1e13, seed=39)  # every request at once
+        capacity = cap_run["achieved_points_per_s"]
+        log(f"unbatched capacity {capacity / 1e9:.2f} G points/s")
+        loads = [f * capacity for f in (0.5, 0.8, 0.95)]
+    runs = {form: [serve(sv, offered, seed=41 + k) for k, offered in enumerate(loads)]
+            for form, sv in servers.items()}
+    for sv in servers.values():
         sv.close()
     sweep = []
     for k, offered in enumerate(loads):
         b, u = runs["batched"][k], runs["unbatched"][k]
         sweep.append({"batched": b, "unbatched": u})
         log(f"offered {offered / 1e9:.2f} G/s: batched {b['achieved_points_per_s'] / 1e9:.2f} G/s "
-            f"p99 {b['latency_ms_p99']} ms; unbatched {u['achieved_points_per_s'] / 1e9:.2f} G/s "
+            f"(busy {b['busy_points_per_s'] / 1e9:.2f}) p99 {b['latency_ms_p99']} ms; unbatched "
+            f"{u['achieved_points_per_s'] / 1e9:.2f} G/s (busy {u['busy_points_per_s'] / 1e9:.2f}) "
             f"p99 {u['latency_ms_p99']} ms")
     top = sweep[-1]["batched"]
     result = {
@@ -336,6 +363,8 @@ def run_served(args):
         "config": {"workload": "16 stream slots, 20 clouds of 10M..200M points, requests of "
                                "50k..5M points, Poisson arrivals, 200 GB admission budget",
                    "points": total, "requests": nreq},
+        "unbatched_capacity_points_per_s": capacity,
+        "offered_fractions_of_capacity": None if capacity is None else [0.5, 0.8, 0.95],
         "sweep": sweep,
     }
     print(json.dumps(result), flush=True)
