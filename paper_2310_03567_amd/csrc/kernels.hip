@@ -1798,8 +1798,13 @@ hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_
 }
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
                              const LaunchShape& sh, hipStream_t s) {
+    // Round 2 of a large pass (a 10M-point batch) has every point of a
+    // pending root to histogram and about 11 tiles per workgroup even at
+    // 4096 workgroups, which hide each other's latency; below 4M items the
+    // launch shape's cap holds (more workgroups only add set-up there).
     const u32 cap = sh.cap[kShapeHist];
-    const u32 g = round == 2u ? grid_for(items + 65536u, 64, cap)
+    const u32 cap2 = items >= (4ull << 20) ? std::max<u32>(cap, 4096u) : cap;
+    const u32 g = round == 2u ? grid_for(items + 65536u, 64, cap2)
                               : grid_for(items / 4u, 32, std::max<u32>(cap / 2u, 32u));
     hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, m, count, round);
     return hipGetLastError();
