@@ -449,6 +449,10 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
 }
 
 // ---------------------------------------------------------- histogram rounds
+// The histogram level counted for a pending root at depth d: kHistLevels
+// levels down, or down to Dmax.
+__device__ __forceinline__ u32 hist_depth(u32 d, u32 Dmax) { return min(kHistLevels, Dmax - d); }
+
 // Relative Morton index, j levels below depth d, of integer position q.
 __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u32 qz) {
     const u32 s = K - d - j;
@@ -457,8 +461,9 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 }
 
 // Round k >= 2: every point whose leaf is a pending root adds one to the
-// root's histogram at each of the kHistLevels levels below it (levels beyond
-// Dmax do not exist).  Round 2 walks all of W; later rounds only the items
+// root's histogram at the deepest of the kHistLevels levels below it that
+// exists (levels beyond Dmax do not); the build kernel sums the levels above
+// it from that one.  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
 __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round, u32 nwg) {
     __shared__ u32 lkey[kLds];
@@ -529,12 +534,13 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
             slot = t.hslot[leaf];
         }
         if (j < nwork) mark[j] = slot != kNone ? 1u : 0u;
-#pragma unroll
-        for (u32 lv = 1; lv <= kHistLevels; ++lv) {
+        {
             u32 key = kNone;
-            if (slot != kNone && depth + lv <= t.Dmax)
+            if (slot != kNone) {  // a pending root is above Dmax: lv >= 1
+                const u32 lv = hist_depth(depth, t.Dmax);
                 key = kHistKey | (slot * kHistEntries + hist_level_offset(lv) +
                                   rel_index(t.K, depth, lv, qx, qy, qz));
+            }
             const Run r = lane_runs(key);
             if (key != kNone && r.rank == 0u) {
                 const u32 e = lds_find_or_insert(lkey, kLdsBits, key, kCountProbe, &lfill);
@@ -641,6 +647,18 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
         if (tid == 0) s_f[0] = kFExists | kFSplit;
         if (tid <= kHistLevels) s_lvsplit[tid] = tid == 0u ? 1u : 0u;
         __syncthreads();
+        // the points were counted at level L only: the levels above it are
+        // the sums of their 8 children (Morton index rel -> 8 rel + o)
+        for (int lv = (int)hist_depth(d0, t.Dmax) - 1; lv >= 1; --lv) {  // uniform
+            const u32 off = hist_level_offset((u32)lv), offc = hist_level_offset((u32)lv + 1u);
+            for (u32 rel = tid; rel < (1u << (3u * (u32)lv)); rel += kWG) {
+                u32 sum = 0u;
+#pragma unroll
+                for (u32 o = 0; o < 8u; ++o) sum += s_h[offc + 8u * rel + o];
+                s_h[off + rel] = sum;
+            }
+            __syncthreads();
+        }
         // flags, level by level (a level exists below the level above's
         // splits); levels below the deepest one with nodes are not visited
         // and the later loops stop at slot nt
