@@ -1151,10 +1151,14 @@ __device__ __forceinline__ void claim_now(const DevTree& t, u64 tag, u32 key, u6
 // same cell with increasing keys add it once; candidates are merged in the
 // tile's LDS table (smallest key per cell), or else listed in the overflow
 // list, and claimed globally, all at once, after the traversal.  Must be
-// reached by the whole wave.
+// reached by the whole wave.  use_table (uniform): merge in the LDS table at
+// all; without it every candidate goes to the overflow list, which a small
+// pass's tiles (a few dozen candidates each, few of them repeated) fill at
+// less cost than the table's compare-and-swap inserts.
 __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u32 node, u32 d,
                                                  u32 word, u32 qx, u32 qy, u32 qz, u32 key,
-                                                 u32 rgba, bool batch_item, u32 lane, u64* ctag,
+                                                 u32 rgba, bool batch_item, u32 lane,
+                                                 bool use_table, u64* ctag,
                                                  u64* cval, u16* s_live, u32* s_nlive,
                                                  u64* s_ovf, u32* s_novf,
                                                  u32 stripe, u32 base_key,
@@ -1170,7 +1174,7 @@ __device__ __forceinline__ void level_candidates(const DevTree& t, bool inner, u
     const u32 pkey = __shfl_up(key, 1);
     const bool cand = tag != kEmptyTag && !(lane > 0u && ptag == tag && pkey < key);
     const u64 val = ((u64)key << 32) | (u64)rgba;
-    if (cand && !cand_insert(ctag, cval, s_live, s_nlive, tag, val, batch_item)) {
+    if (cand && !(use_table && cand_insert(ctag, cval, s_live, s_nlive, tag, val, batch_item))) {
         const u32 o = atomicAdd(s_novf, 1u);
         if (o < kOvf) {  // claimed with the table's entries
             s_ovf[2u * o] = tag;
@@ -1345,7 +1349,7 @@ __device__ __forceinline__ void flush_staged(const DevTree& t, u32 stripe, u32* 
 // voxel counts are summed in LDS and flushed once per workgroup, and claimed
 // cells are staged in LDS and appended with one atomic per workgroup on one
 // of kStripes counters (workgroup id mod kStripes, i.e. one per XCD).
-__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count) {
+__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count, u32 use_table) {
     __shared__ u32 s_claims[kClaimBuf];
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
@@ -1433,9 +1437,9 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
                 desc = false;
             }
             level_candidates(t, inner, ed & ~kDirInner, d, wd, qx, qy, qz, key, rec.w,
-                             batch_item, lane, s_ctag, s_cval, s_live, &s_nlive, s_ovf,
-                             &s_novf, stripe,
-                             base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
+                             batch_item, lane, use_table != 0u, s_ctag, s_cval, s_live,
+                             &s_nlive, s_ovf, &s_novf, stripe, base_key, s_claims, &s_nclaims,
+                             s_vkey, s_vcnt, &s_vfill);
         }
         // Below the directory: dependent walk through child[].
         u32 node = 0u;
@@ -1451,9 +1455,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
             u32 word = ~0u;
             if (inner) word = grid_of(t, node)[cell_lin(qx, qy, qz, t.Dmax - d, t.r, rmask) >> 5];
             level_candidates(t, inner, node, d, word, qx, qy, qz, key, rec.w, batch_item, lane,
-                             s_ctag, s_cval, s_live, &s_nlive, s_ovf, &s_novf, stripe,
-                             base_key, s_claims,
-                             &s_nclaims, s_vkey, s_vcnt, &s_vfill);
+                             use_table != 0u, s_ctag, s_cval, s_live, &s_nlive, s_ovf, &s_novf,
+                             stripe, base_key, s_claims, &s_nclaims, s_vkey, s_vcnt, &s_vfill);
             if (inner) node = ch + octant_of(qx, qy, qz, t.K - 1u - d);
         }
         if (desc) leaf = node;
@@ -1863,7 +1866,10 @@ hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
 hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                                hipStream_t s) {
     const u32 g = grid_for(items + 4096u, 64, sh.cap[kShapeSample]);
-    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count);
+    // the LDS candidate table pays on large passes (a 10M-point scan's tiles
+    // meet hundreds of repeated cells), not on 1M-point ones
+    const u32 use_table = items >= (4ull << 20) ? 1u : 0u;
+    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count, use_table);
     return hipGetLastError();
 }
 hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,

@@ -114,6 +114,32 @@ def test_every_batch_matches_sequential_oracle_on_planes():
     assert st["num_inner"] >= 1
 
 
+def test_large_passes_with_the_candidate_table_match_sequential_oracle():
+    """Passes of 4.5M points take the kernels' large-pass shape (the LDS
+    candidate table for voxel claims, the widened histogram round); small
+    passes do not.  Two such passes of a scan-ordered dense cloud (points of
+    a strip in random order, so tiles overflow the candidate table) against
+    the sequential oracle, after each pass."""
+    import pointgen
+
+    p = pointgen.dense_scan(9_000_000, seed=5)
+    cfg = LodConfig(root_size=64.0, leaf_capacity=20_000, grid_bits=6, max_depth=12,
+                    chunk_capacity=500)
+    dev = to_device(p)
+    o = IncrementalOracle(cfg)
+    with make_octree(cfg, arena_bytes=4 << 30, max_batch=5_000_000, spill_capacity=8 << 20,
+                     backlog_capacity=8 << 20, max_nodes=1 << 18) as tree:
+        for k in range(2):
+            log(f"case: large pass {k}, 4.5M dense-scan points")
+            b = slice(k * 4_500_000, (k + 1) * 4_500_000)
+            tree.insert(dev[b.start * 16:b.stop * 16])
+            o.insert(p[b])
+            assert_trees_equal(canonical(tree), o.canonical(), f"after large pass {k}")
+        st = tree.stats()
+    o.close()
+    assert st["status_bits"] == 0 and st["num_inner"] > 1 and st["max_spilled"] > 0
+
+
 @pytest.mark.parametrize("parts", [[1_000_000], [250_000] * 4, [1, 99_999, 400_000, 500_000],
                                    [333_333, 333_333, 333_334]])
 def test_batch_partition_invariance_on_planes(parts):
