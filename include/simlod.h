@@ -426,7 +426,17 @@ typedef struct simlod_server_config {
     uint32_t max_per_pass;      /* requests per pass (0 = one per stream);
                                    1 serves requests one at a time, in
                                    arrival order: the unbatched form */
-    uint32_t reserved;
+    uint32_t pass_points;       /* time budget of a pass, in points: a request
+                                   in device memory larger than this is
+                                   inserted over several passes, pass_points
+                                   at a time (the paper's per-frame budget
+                                   with the rest resumed next frame, section
+                                   "Evaluation"), so small requests of other
+                                   streams need not wait for one large
+                                   update; it completes with its last part.
+                                   The octree is the same (consecutive
+                                   passes of one sequence).  0 = no budget;
+                                   requests in host memory are never cut. */
     uint64_t staging_bytes;     /* device staging for requests in host memory
                                    (allocated at create; 0 = host requests
                                    are rejected) */

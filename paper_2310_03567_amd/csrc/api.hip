@@ -1469,6 +1469,10 @@ struct ServerRequest {
     bool ready = true;            // host requests: the copy has been enqueued
     u64 stage_off = 0, stage_len = 0;  // staging range of a host request
     hipEvent_t up_ev = nullptr;   // host requests: after the copy
+    // pass budget: points of a queued request already given to passes; in a
+    // pass, whether this part is the request's last (the one that completes it)
+    u32 taken = 0;
+    bool last = true;
 };
 
 struct ServerSlot {
@@ -1662,7 +1666,7 @@ std::vector<ServerRequest> server_pick(simlod_server* sv) {
             ServerRequest& r = sl.queue.front();
             sv->results[r.ticket - 1] = RequestResult{1, SIMLOD_ERR_POISONED, 0.0};
             if (r.ready) release_upload(sv, r);  // else the uploader frees it
-            sl.queued_points -= r.n;
+            sl.queued_points -= r.n - r.taken;
             sl.queue.pop_front();
             ++sv->completed;
         }
@@ -1675,13 +1679,27 @@ std::vector<ServerRequest> server_pick(simlod_server* sv) {
         });
         heads.resize(lim);
     }
+    // the pass budget cuts a request in device memory into parts of at most
+    // pass_points points, one per pass, in order; it stays at the head of its
+    // stream's queue until its last part is taken
+    const u32 budget = sv->cfg.pass_points;
     std::vector<ServerRequest> out;
     for (u32 i : heads) {
         ServerSlot& sl = sv->slots[i];
-        out.push_back(sl.queue.front());
-        sl.queue.pop_front();
-        sl.queued_points -= out.back().n;
+        ServerRequest& head = sl.queue.front();
+        const u32 rest = head.n - head.taken;
+        const u32 take = (budget && !head.host) ? std::min(rest, budget) : rest;
+        ServerRequest part = head;
+        part.pts = head.pts + head.taken;
+        part.n = take;
+        part.last = take == rest;
+        if (part.last)
+            sl.queue.pop_front();
+        else
+            head.taken += take;
+        sl.queued_points -= take;
         sl.inflight += 1;
+        out.push_back(part);
     }
     return out;
 }
@@ -1786,10 +1804,16 @@ void server_complete(simlod_server* sv) {
                 sl.h->poisoned = 1;
                 sl.h->sticky = st;
             }
+            sl.inflight -= 1;
+            if (!r.last) {  // an earlier part of a request cut by the pass budget
+                RequestResult& rr = sv->results[r.ticket - 1];
+                if (st && !rr.done) rr.status = st;  // reported with the last part
+                continue;
+            }
             const double ms =
                 std::chrono::duration<double, std::milli>(now - r.t_submit).count();
-            sv->results[r.ticket - 1] = RequestResult{1, st, ms};
-            sl.inflight -= 1;
+            const int prior = sv->results[r.ticket - 1].status;  // an earlier part's error
+            sv->results[r.ticket - 1] = RequestResult{1, st ? st : prior, ms};
             ++sv->completed;
             if (r.stage_len) release_upload(sv, ps->reqs[i]);
         }

@@ -90,7 +90,7 @@ class StatsData(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("max_streams", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("max_per_pass", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("staging_bytes", ctypes.c_uint64)]
+                ("pass_points", ctypes.c_uint32), ("staging_bytes", ctypes.c_uint64)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -512,9 +512,10 @@ class Server:
     """Continuous-batching insertion server (``simlod_server_*``)."""
 
     def __init__(self, max_streams: int, hbm_budget: int, max_per_pass: int = 0, device: int = 0,
-                 staging_bytes: int = 0):
+                 staging_bytes: int = 0, pass_points: int = 0):
         cfg = ServerConfig(device=device, max_streams=max_streams, hbm_budget=hbm_budget,
-                           max_per_pass=max_per_pass, reserved=0, staging_bytes=staging_bytes)
+                           max_per_pass=max_per_pass, pass_points=pass_points,
+                           staging_bytes=staging_bytes)
         h = ctypes.c_void_p()
         _check(lib.simlod_server_create(ctypes.byref(cfg), ctypes.byref(h)), "simlod_server_create")
         self.handle = h.value

@@ -50,7 +50,8 @@ def _simlod_cfg(cfg: LodConfig, max_batch, arena_bytes=256 << 20):
                               spill_capacity=1 << 19, backlog_capacity=1 << 19)
 
 
-def _serve(streams, max_per_pass, seed, where=None, staging=0, arena_bytes=256 << 20):
+def _serve(streams, max_per_pass, seed, where=None, staging=0, arena_bytes=256 << 20,
+           pass_points=0):
     """where[k]: "device" (default), "pinned" or "pageable" host memory for
     stream k's requests."""
     import torch
@@ -59,7 +60,7 @@ def _serve(streams, max_per_pass, seed, where=None, staging=0, arena_bytes=256 <
 
     where = where or ["device"] * len(streams)
     with simlod.Server(max_streams=8, hbm_budget=64 << 30, max_per_pass=max_per_pass,
-                       staging_bytes=staging) as sv:
+                       staging_bytes=staging, pass_points=pass_points) as sv:
         ids = [sv.open(_simlod_cfg(cfg, 40_000, arena_bytes)) for cfg, _ in streams]
         assert None not in ids
         devs = []
@@ -124,6 +125,31 @@ def test_served_streams_equal_their_oracle(max_per_pass):
     if max_per_pass == 1:
         assert counters["passes"] == len(lat)
     log(f"passes {counters['passes']} requests {len(lat)} p50 {np.percentile(lat, 50):.3f} ms")
+
+
+def test_pass_budget_cuts_requests_into_parts_with_the_same_octrees():
+    """A pass budget of 7,001 points: device requests of up to 40k points are
+    inserted over several passes, each part continuing the stream's key
+    sequence, mixed with uncut host-memory requests; every stream's octree is
+    still exactly its oracle's, and each request completes once."""
+    rng = np.random.default_rng(35)
+    streams = []
+    for k in range(5):
+        cfg = LodConfig(leaf_capacity=int(rng.choice([20, 50, 500])),
+                        grid_bits=int(rng.integers(1, 5)), max_depth=int(rng.integers(4, 10)),
+                        chunk_capacity=int(rng.choice([3, 64, 1000])))
+        streams.append((cfg, _cloud(rng, int(rng.integers(20_000, 100_000)))))
+    where = ["device", "pinned", "device", "device", "pageable"]
+    log("case: served with a pass budget of 7,001 points, 5 streams")
+    for max_per_pass in (0, 1):
+        got, lat, counters = _serve(streams, max_per_pass, seed=36, where=where,
+                                    staging=2 << 20, arena_bytes=1 << 30, pass_points=7_001)
+        for k, ((cfg, p), t) in enumerate(zip(streams, got)):
+            assert_trees_equal(t, O1.build(p, cfg), f"stream {k} ({where[k]}) n={len(p)}")
+        assert counters["points"] == sum(len(p) for _, p in streams)
+        assert counters["completed"] == len(lat)
+        if max_per_pass == 1:  # one part per pass: requests above the budget took several
+            assert counters["passes"] > len(lat)
 
 
 def test_admission_by_budget_and_slots():
