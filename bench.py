@@ -323,30 +323,26 @@ def run_served(args):
                 "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                 "seconds": round(el, 3)}
 
-    # one server per form; a warm-up run allocates the octrees, which the
-    # measured runs then reuse from the server's pool
-    # batched_budget: batched, with a pass budget of 1M points (a request of
-    # up to 5M is inserted over several passes, so small requests of other
-    # streams do not wait behind it)
-    forms = (("batched", 0, 0), ("unbatched", 1, 0), ("batched_budget", 0, 1_000_000))
-    servers = {form: simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=per_pass,
-                                   pass_points=budget)
-               for form, per_pass, budget in forms}
+    # one server per form, one form at a time (each pools its octrees in
+    # device memory); a warm-up run allocates the octrees, which the measured
+    # runs then reuse from the server's pool.  batched_budget: batched, with a
+    # pass budget of 1M points (a request of up to 5M points is inserted over
+    # several passes, so small requests of other streams do not wait behind
+    # it).  The unbatched form goes first: its capacity sets the loads.
+    forms = (("unbatched", 1, 0), ("batched", 0, 0), ("batched_budget", 0, 1_000_000))
     capacity = None
-    if args.offered:
-        loads = [float(x) * 1e9 for x in str(args.offered).split(",")]
-        for sv in servers.values():
-            serve(sv, loads[0], seed=40)
-    else:
-        for sv in servers.values():
-            serve(sv, 1e13, seed=40)  # warm-up
-        cap_run = serve(servers["unbatched"], 1e13, seed=39)  # every request at once
-        capacity = cap_run["achieved_points_per_s"]
-        log(f"unbatched capacity {capacity / 1e9:.2f} G points/s")
-        loads = [f * capacity for f in (0.5, 0.8, 0.95)]
-    runs = {form: [serve(sv, offered, seed=41 + k) for k, offered in enumerate(loads)]
-            for form, sv in servers.items()}
-    for sv in servers.values():
+    loads = [float(x) * 1e9 for x in str(args.offered).split(",")] if args.offered else None
+    runs = {}
+    for form, per_pass, budget in forms:
+        sv = simlod.Server(max_streams=slots, hbm_budget=200 << 30, max_per_pass=per_pass,
+                           pass_points=budget)
+        serve(sv, 1e13 if loads is None else loads[0], seed=40)  # warm-up
+        if loads is None:
+            cap_run = serve(sv, 1e13, seed=39)  # every request at once
+            capacity = cap_run["achieved_points_per_s"]
+            log(f"unbatched capacity {capacity / 1e9:.2f} G points/s")
+            loads = [f * capacity for f in (0.5, 0.8, 0.95)]
+        runs[form] = [serve(sv, offered, seed=41 + k) for k, offered in enumerate(loads)]
         sv.close()
     sweep = []
     for k, offered in enumerate(loads):
