@@ -74,6 +74,7 @@ SAMPLE_STORE_BYTES_PER_SPILLED = 4
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_store_{}_hbm_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03567_amd", "csrc", "kernels.hip")
+BUILD_SCRIPT = os.path.join(ROOT, "paper_2310_03567_amd", "build.py")  # compiler flags
 
 
 def log(msg):
@@ -83,7 +84,8 @@ def log(msg):
 def measured_traffic(name):
     """HBM bytes per k_sample_store launch on workload ``name`` from the
     committed rocprofv3 summary (FETCH_SIZE + WRITE_SIZE scaled by a plain
-    copy), or None when the summary was taken on a different kernel source."""
+    copy), or None when the summary was taken on a different kernel source
+    or with other compiler flags."""
     import hashlib
 
     try:
@@ -92,7 +94,9 @@ def measured_traffic(name):
         return None
     fields = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith(" "))
     want = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernels_sha256", "").strip() != want:
+    flags = hashlib.sha256(open(BUILD_SCRIPT, "rb").read()).hexdigest()
+    if (fields.get("kernels_sha256", "").strip() != want
+            or fields.get("build_sha256", "").strip() != flags):
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
