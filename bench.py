@@ -223,6 +223,17 @@ def run_batched(args):
     print(json.dumps(result), flush=True)
 
 
+def busy_seconds(spans):
+    """Length of the union of the (start, end) intervals: the time in which
+    at least one request was outstanding."""
+    busy, end = 0.0, float("-inf")
+    for a, b in sorted(spans):
+        if b > end:
+            busy += b - max(a, end)
+            end = b
+    return busy
+
+
 def run_served(args):
     """Continuous batching under load.  16 stream slots serve 20 clouds of
     10M..200M points (log-uniform; aerial or dense scan by seed), each cut
@@ -312,11 +323,7 @@ def run_served(args):
         c = sv.counters()
         lat = np.array(lat)
         passes = int(c["passes"] - c0["passes"])
-        busy, end = 0.0, -1.0  # union of the outstanding intervals
-        for a, b in sorted(spans):
-            if b > end:
-                busy += b - max(a, end)
-                end = b
+        busy = busy_seconds(spans)
         return {"offered_points_per_s": round(offered_pps, 1),
                 "achieved_points_per_s": round(done_points / el, 1),
                 "busy_points_per_s": round(done_points / max(busy, 1e-9), 1),
