@@ -133,10 +133,11 @@ u32 tag_bits_for(const simlod_config* c) {
     return bit_length((u64)c->max_nodes - 1u) + 3u * c->grid_bits;
 }
 
-// Claim-table entries: twice the backlog, and enough that a cell identity's
-// bits beyond the table index fit the claim word's tag (kRemBits).
+// Claim-table entries: twice the backlog (at least one 8-entry bucket), and
+// enough that a cell identity's bits beyond the table index fit the claim
+// word's tag (kRemBits).
 u64 hash_entries_for(const simlod_config* c) {
-    u64 e = next_pow2(2 * c->backlog_capacity);
+    u64 e = std::max<u64>(next_pow2(2 * c->backlog_capacity), 8u);
     const u32 tb = tag_bits_for(c);
     if (tb > kRemBits) e = std::max<u64>(e, 1ull << (tb - kRemBits));
     return e;

@@ -1001,7 +1001,7 @@ __device__ __forceinline__ u64 cell_identity(const DevTree& t, u64 ltag) {
 __device__ __forceinline__ bool claim_probe(const DevTree& t, u32 home, u32 rem, u32 key, u32 d0,
                                             u32& slot, bool& fresh) {
     for (u32 d = d0; d < (1u << kDistBits); ++d) {
-        const u32 h = (home + d) & t.hmask;
+        const u32 h = claim_step(t, home, d);
         const u32 tg = (rem << kDistBits) | d;
         const u64 mine = ((u64)tg << 32) | key;
         u64* w = claim_word_at(t, h);

@@ -150,7 +150,7 @@ struct DevTree {
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
     GPtr<u32> item_leaf;      // per batch item: its leaf in the first round
     u32 active_cap;
-    GPtr<u64> hent;           // voxel claim table, 16-byte entries (one cache line):
+    GPtr<u64> hent;           // voxel claim table, 16-byte entries, 8 to a bucket:
                          // [2h] = claim word (tag << 32 | key), min-reduced,
                          // [2h + 1] = (key << 32 | rgba) of spilled claimants,
                          // min-reduced (see claim_home)
@@ -204,14 +204,20 @@ __device__ __forceinline__ u64* claim_spill_at(const DevTree& t, u32 h) {
 }
 
 // Claim table addressing.  A cell's identity T = node << 3r | cell has
-// tag_bits bits.  An invertible mix of those bits (multiply by an odd
-// constant mod 2^n, xor-shift by at least n/2, multiply again) gives the
-// home entry (its top hash_bits bits) and a remainder (the other bits, at
-// most kRemBits); an entry then holds (remainder << kDistBits | probe
-// distance) as its 32-bit tag, which together with the entry's index
-// determines T.  So one 64-bit word (tag << 32 | key) carries both the
-// cell and the smallest key claimed for it, and a claim is one atomic.
-constexpr u32 kDistBits = 7;  // linear probing up to 127 entries past home
+// tag_bits bits.  The table is made of buckets of 8 entries (one 128-byte
+// line): the 8 cells of a 2x2x2 block of a node's grid share a bucket, each
+// at its own position in it, so that the claims of neighbouring points
+// (which meet neighbouring cells) share L2 lines.  T splits into the block's
+// identity G (tag_bits - 3 bits) and the cell's position in the block.  An
+// invertible mix of G's bits (multiply by an odd constant mod 2^n, xor-shift
+// by at least n/2, multiply again) gives the home bucket (its top bits) and
+// a remainder (the other bits, at most kRemBits).  A cell probes its own
+// position in the home bucket and the buckets after it; an entry then holds
+// (remainder << kDistBits | probe distance) as its 32-bit tag, which
+// together with the entry's index determines T.  So one 64-bit word
+// (tag << 32 | key) carries both the cell and the smallest key claimed for
+// it, and a claim is one atomic.  (r = 0, one cell per node: buckets of 1.)
+constexpr u32 kDistBits = 7;  // linear probing up to 127 buckets past home
 constexpr u32 kRemBits = 24;  // the tag stays below 2^31, never the empty word's
 constexpr u64 kMixA = 0x9E3779B97F4A7C15ull;
 constexpr u64 kMixAinv = 0xF1DE83E19937733Dull;  // kMixA * kMixAinv = 1 mod 2^64
@@ -237,20 +243,66 @@ __device__ __forceinline__ u32 rem_bits_of(const DevTree& t) {
     return t.tag_bits > t.hash_bits ? t.tag_bits - t.hash_bits : 0u;
 }
 
-// Home entry and remainder of identity T.
+// log2 of the entries of a bucket
+__device__ __forceinline__ u32 claim_sub_bits(const DevTree& t) { return t.r ? 3u : 0u; }
+
+// Identity T -> (block identity G, position of the cell in its 2x2x2 block).
+__device__ __forceinline__ void claim_split(const DevTree& t, u64 T, u64& G, u32& sub) {
+    const u32 r = t.r;
+    if (!r) {
+        G = T;
+        sub = 0u;
+        return;
+    }
+    const u32 m = t.R - 1u;
+    const u32 cell = (u32)(T & low_bits(3u * r));
+    const u64 node = T >> (3u * r);
+    const u32 cx = cell & m, cy = (cell >> r) & m, cz = cell >> (2u * r);
+    sub = (cx & 1u) | ((cy & 1u) << 1) | ((cz & 1u) << 2);
+    const u32 q = r - 1u;
+    G = (node << (3u * q)) | (u64)((cx >> 1) | ((cy >> 1) << q) | ((cz >> 1) << (2u * q)));
+}
+
+// Inverse of claim_split.
+__device__ __forceinline__ u64 claim_join(const DevTree& t, u64 G, u32 sub) {
+    const u32 r = t.r;
+    if (!r) return G;
+    const u32 q = r - 1u;
+    const u32 qm = (1u << q) - 1u;
+    const u32 blk = (u32)(G & low_bits(3u * q));
+    const u64 node = G >> (3u * q);
+    const u32 cx = ((blk & qm) << 1) | (sub & 1u);
+    const u32 cy = (((blk >> q) & qm) << 1) | ((sub >> 1) & 1u);
+    const u32 cz = ((blk >> (2u * q)) << 1) | (sub >> 2);
+    return (node << (3u * r)) | (u64)(cx | (cy << r) | (cz << (2u * r)));
+}
+
+// Home entry (the cell's position in its home bucket) and remainder of
+// identity T.
 __device__ __forceinline__ void claim_home(const DevTree& t, u64 T, u32& home, u32& rem) {
-    const u64 m = tag_mix(T, t.tag_bits);
+    u64 G;
+    u32 sub;
+    claim_split(t, T, G, sub);
+    const u32 sb = claim_sub_bits(t);
+    const u64 m = tag_mix(G, t.tag_bits - sb);
     const u32 rb = rem_bits_of(t);
-    home = (u32)(m >> rb) & t.hmask;
+    home = (((u32)(m >> rb) & (t.hmask >> sb)) << sb) | sub;
     rem = (u32)(m & low_bits(rb));
+}
+
+// Entry at probe distance d (buckets) from home entry `home`.
+__device__ __forceinline__ u32 claim_step(const DevTree& t, u32 home, u32 d) {
+    return (home + (d << claim_sub_bits(t))) & t.hmask;
 }
 
 // Identity T of the cell whose claim word at entry h carries tag tg.
 __device__ __forceinline__ u64 claim_identity(const DevTree& t, u32 h, u32 tg) {
     const u32 d = tg & ((1u << kDistBits) - 1u);
-    const u64 home = (u64)((h - d) & t.hmask);
+    const u32 sb = claim_sub_bits(t);
+    const u64 hb = (u64)(((h - (d << sb)) & t.hmask) >> sb);
     const u32 rb = rem_bits_of(t);
-    return tag_unmix((home << rb) | (u64)(tg >> kDistBits), t.tag_bits);
+    const u64 G = tag_unmix((hb << rb) | (u64)(tg >> kDistBits), t.tag_bits - sb);
+    return claim_join(t, G, h & ((1u << sb) - 1u));
 }
 
 __device__ __forceinline__ uint8_t* block_ptr(const DevTree& t, u32 blk) {
