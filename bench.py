@@ -73,8 +73,21 @@ SAMPLE_STORE_BYTES_PER_SPILLED = 4
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sample_store_{}_hbm_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_03567_amd", "csrc", "kernels.hip")
+# the device code: the kernels and the headers they inline
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_03567_amd", "csrc", f)
+                  for f in ("kernels.hip", "octree_device.hpp", "launch.hpp")]
 BUILD_SCRIPT = os.path.join(ROOT, "paper_2310_03567_amd", "build.py")  # compiler flags
+
+
+def kernels_sha256():
+    """SHA-256 over the device sources (name and contents of each, in order)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(os.path.basename(f).encode() + b"\0")
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -93,7 +106,7 @@ def measured_traffic(name):
     except OSError:
         return None
     fields = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith(" "))
-    want = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    want = kernels_sha256()
     flags = hashlib.sha256(open(BUILD_SCRIPT, "rb").read()).hexdigest()
     if (fields.get("kernels_sha256", "").strip() != want
             or fields.get("build_sha256", "").strip() != flags):
