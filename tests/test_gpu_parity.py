@@ -140,6 +140,31 @@ def test_large_passes_with_the_candidate_table_match_sequential_oracle():
     assert st["status_bits"] == 0 and st["num_inner"] > 1 and st["max_spilled"] > 0
 
 
+@pytest.mark.parametrize("order", ["morton", "random"])
+def test_aerial_orders_match_sequential_oracle(order):
+    """The aerial height field in plain Morton order (few leaves per tile)
+    and in random order (nearly every point of a tile in another leaf and
+    another claim cell): 3M points in six 500k-point passes, T = 20k, against
+    the sequential oracle after every pass."""
+    import pointgen
+
+    n, B = 3_000_000, 500_000
+    p = pointgen.aerial(n, seed=11, order=order, batch=B)
+    cfg = LodConfig(root_size=1024.0, leaf_capacity=20_000)
+    dev = to_device(p)
+    o = IncrementalOracle(cfg)
+    with make_octree(cfg, arena_bytes=2 << 30, max_batch=B, backlog_capacity=4 << 20) as tree:
+        for k in range(n // B):
+            log(f"case: aerial {order} order, pass {k}")
+            b = slice(k * B, (k + 1) * B)
+            tree.insert(dev[b.start * 16:b.stop * 16])
+            o.insert(p[b])
+            assert_trees_equal(canonical(tree), o.canonical(), f"{order}: after pass {k}")
+        st = tree.stats()
+    o.close()
+    assert st["status_bits"] == 0 and st["num_points"] == n and st["num_inner"] > 8
+
+
 @pytest.mark.parametrize("parts", [[1_000_000], [250_000] * 4, [1, 99_999, 400_000, 500_000],
                                    [333_333, 333_333, 333_334]])
 def test_batch_partition_invariance_on_planes(parts):
