@@ -284,6 +284,9 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
                          [&] { return launch_count_leaves(ga, items, sh, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(M, cnt, items, s); });
+    if (e == hipSuccess && items >= kGroupMinItems)
+        e = timed(tm, SIMLOD_KERNEL_GROUP_BATCH, s,
+                  [&] { return launch_group_batch(M, cnt, items, sh, s); });
     if (rounds >= 2u && e == hipSuccess) {
         e = timed(tm, SIMLOD_KERNEL_COUNT_HIST, s,
                   [&] { return launch_count_hist(M, cnt, items, 2u, sh, s); });
@@ -293,7 +296,7 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
     // the rare later rounds share the leaves' chunk allocation's launch
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_ALLOC_POINTS, s,
-                  [&] { return launch_rounds_alloc(M, cnt, 3u, rounds, s); });
+                  [&] { return launch_rounds_alloc(M, cnt, items, 3u, rounds, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_SAMPLE_STORE, s,
                   [&] { return launch_sample_store(M, cnt, items, sh, s); });
@@ -467,6 +470,9 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.hist, (u64)hist_slots * kHistEntries) && dalloc(h, &t.final_list, N) &&
               dalloc(h, &t.vtouched, N) && dalloc(h, &t.amask[0], work) &&
               dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, cfg->max_batch) &&
+              (cfg->max_batch < kGroupMinItems ||
+               (dalloc(h, &t.grp_rec, cfg->max_batch) && dalloc(h, &t.grp_index, cfg->max_batch) &&
+                dalloc(h, &t.grp_leaf, cfg->max_batch) && dalloc(h, &t.grp_next, N))) &&
               dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
               dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 2);  // + pass barrier words

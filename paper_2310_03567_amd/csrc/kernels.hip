@@ -65,11 +65,16 @@ __device__ __forceinline__ u32 xcd_block(u32 g) {
     return (b & 7u) * (g >> 3) + (b >> 3);
 }
 
-__device__ __forceinline__ void fetch_work(const DevTree& t, const uint4* batch, u32 S,
-                                           u32 base_key, u32 i, uint4& rec, u32& key) {
+// Work item i: a spilled point (i < S) or a batch point.  grouped: the batch
+// part of the list is in the leaf-grouped order (grp_rec, grp_index).
+__device__ __forceinline__ void fetch_work(const DevTree& t, const uint4* batch, bool grouped,
+                                           u32 S, u32 base_key, u32 i, uint4& rec, u32& key) {
     if (i < S) {
         rec = t.spill_rec[i];
         key = t.spill_key[i];
+    } else if (grouped) {
+        rec = t.grp_rec[i - S];
+        key = base_key + t.grp_index[i - S];
     } else {
         rec = batch[i - S];
         key = base_key + (i - S);
@@ -366,7 +371,10 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
 // spill buffer (they are re-inserted with the batch) and its chunks pushed to
 // the pool (section "Chunks and the Chunk Pool").  Any other counted leaf is
 // final for the pass and listed with its number of new points.
-__global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count) {
+// grouped (uniform): the pass groups its batch by leaf; each counted leaf of
+// an octree that keeps the grouped order also gets its group's first
+// position (groups in any order).
+__global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count, u32 grouped) {
     __shared__ u32 s_dec[2];
     __shared__ i32 s_pool;
     __shared__ u32 s_pre[kMaxMembers + 1u];
@@ -384,6 +392,7 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
             const u32 cn = t.cnt[L];
             const u32 stored = t.count[L];
             const u32 depth = t.geo[L].w;
+            if (grouped && t.grp_next) t.grp_next[L] = atomicAdd(&ctr->bucket_top, cn);
             u32 pend = 0u, slot = 0u, sbase = 0u;
             if ((u64)stored + cn > (u64)t.T && depth < t.Dmax) {
                 slot = atomicAdd(&ctr->hist_top, 1u);
@@ -448,6 +457,94 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
     }
 }
 
+// ---------------------------------------------------------- leaf-grouped order
+// Large passes: the batch is copied into the order grouped by first-round
+// leaf (each leaf's group at the position the split kernel gave it; within a
+// group in the order the windows reserve their places), with each point's
+// batch index and leaf; the later kernels read the batch part of the work
+// list from there.  A workgroup takes windows of kGroupTiles tiles: it
+// counts the window's points per leaf in LDS, reserves each leaf's places
+// with one atomic (same-address atomics serialize, and every window of a
+// dense strip meets the same few leaves), then places the points.
+constexpr u32 kGroupTiles = 8;
+constexpr u32 kGroupBits = 11;  // table entries >= the points of a window
+static_assert((1u << kGroupBits) >= kGroupTiles * 256u, "a window's leaves always fit");
+
+__global__ __launch_bounds__(256) void k_group_batch(const Member* M, u32 count) {
+    __shared__ u32 s_key[1u << kGroupBits], s_cnt[1u << kGroupBits], s_base[1u << kGroupBits];
+    __shared__ u32 s_pre[kMaxMembers + 1u];
+    const u32 tid = threadIdx.x;
+    for (u32 i = tid; i < (1u << kGroupBits); i += kWG) {
+        s_key[i] = kNone;
+        s_cnt[i] = 0u;
+    }
+    const u32 nwin = member_prefix(count, s_pre, [&](u32 c) {
+        const DevTree* tp = M[c].tree;
+        const u32 per = kGroupTiles * kWG;
+        return tp->ctr->status || !tp->grp_rec ? 0u : (M[c].n + per - 1u) / per;
+    });
+    for (u32 win = xcd_block(gridDim.x); win < nwin; win += gridDim.x) {
+        const u32 c = member_of(s_pre, count, win);
+        const DevTree t = tree_of(M, c);
+        const u32 n = M[c].n;
+        const u32 j0 = (win - s_pre[c]) * (kGroupTiles * kWG) + tid;
+        u32 leaf[kGroupTiles];
+        uint4 rec[kGroupTiles];
+#pragma unroll
+        for (u32 k = 0; k < kGroupTiles; ++k) {
+            const u32 j = j0 + k * kWG;
+            leaf[k] = kNone;
+            rec[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (j < n) {
+                leaf[k] = t.item_leaf[j];
+                rec[k] = M[c].batch[j];
+            }
+        }
+        // the window's points per leaf
+#pragma unroll
+        for (u32 k = 0; k < kGroupTiles; ++k) {
+            const Run r = lane_runs(leaf[k]);
+            if (leaf[k] != kNone && r.rank == 0u)
+                atomicAdd(&s_cnt[lds_find_or_insert(s_key, kGroupBits, leaf[k])], r.len);
+        }
+        __syncthreads();
+        for (u32 i = tid; i < (1u << kGroupBits); i += kWG) {
+            const u32 k = s_key[i];
+            if (k != kNone) s_base[i] = atomicAdd(&t.grp_next[k], s_cnt[i]);
+            s_cnt[i] = 0u;  // from here on: places taken within the window
+        }
+        __syncthreads();
+#pragma unroll
+        for (u32 k = 0; k < kGroupTiles; ++k) {
+            const u32 j = j0 + k * kWG;
+            const Run r = lane_runs(leaf[k]);
+            u32 e = kNone, r0 = 0u;
+            if (leaf[k] != kNone && r.rank == 0u) {
+                e = lds_find_or_insert(s_key, kGroupBits, leaf[k]);  // present: counted above
+                r0 = atomicAdd(&s_cnt[e], r.len);
+            }
+            e = __shfl(e, r.head);
+            r0 = __shfl(r0, r.head) + r.rank;
+            if (j < n) {
+                const u32 pos = leaf[k] != kNone ? s_base[e] + r0 : kNone;
+                if (pos < n) {
+                    t.grp_rec[pos] = rec[k];
+                    t.grp_index[pos] = j;
+                    t.grp_leaf[pos] = leaf[k];
+                } else {  // the first round's counts and leaves disagree
+                    set_status(t, SIMLOD_OVF_INTERNAL);
+                }
+            }
+        }
+        __syncthreads();
+        for (u32 i = tid; i < (1u << kGroupBits); i += kWG) {
+            s_key[i] = kNone;
+            s_cnt[i] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------- histogram rounds
 // The histogram level counted for a pending root at depth d: kHistLevels
 // levels down, or down to Dmax.
@@ -465,7 +562,10 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // exists (levels beyond Dmax do not); the build kernel sums the levels above
 // it from that one.  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
-__device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round, u32 nwg) {
+// grouped (uniform): the pass's batch is in the leaf-grouped order (octrees
+// that keep it).
+__device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round, u32 nwg,
+                                                u32 grouped) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
@@ -491,6 +591,7 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
         const uint8_t* prev = round >= 3u ? ((round & 1u) ? t.amask[0] : t.amask[1]) : nullptr;
         uint8_t* mark = (round & 1u) ? t.amask[1] : t.amask[0];
         const u32 j = (tile - s_pre[c]) * kWG + tid;
+        const bool grp = grouped && t.grp_rec;
         u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
         if (j < S && !prev) {
             // round 2, a spilled item: its leaf is the spill job whose range
@@ -519,16 +620,16 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
             // round 2, a batch item: the tree has not changed since the
             // first round, so the item's leaf is the one recorded then; only
             // items of pending roots need their record
-            const u32 leaf = t.item_leaf[j - S];
+            const u32 leaf = grp ? t.grp_leaf[j - S] : t.item_leaf[j - S];
             slot = t.hslot[leaf];
             if (slot != kNone) {
-                quantize3(t, M[c].batch[j - S], qx, qy, qz);
+                quantize3(t, grp ? t.grp_rec[j - S] : M[c].batch[j - S], qx, qy, qz);
                 depth = t.geo[leaf].w;
             }
         } else if (j < nwork && prev[j]) {
             uint4 rec;
             u32 key;
-            fetch_work(t, M[c].batch, S, M[c].base_key, j, rec, key);
+            fetch_work(t, M[c].batch, grp, S, M[c].base_key, j, rec, key);
             quantize3(t, rec, qx, qy, qz);
             const u32 leaf = find_leaf(t, qx, qy, qz, depth);
             slot = t.hslot[leaf];
@@ -794,8 +895,9 @@ __device__ __forceinline__ void build_body(const Member* M, u32 count, u32 round
     }
 }
 
-__global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round) {
-    count_hist_body(M, count, round, gridDim.x);
+__global__ __launch_bounds__(256) void k_count_hist(const Member* M, u32 count, u32 round,
+                                                    u32 grouped) {
+    count_hist_body(M, count, round, gridDim.x, grouped);
 }
 
 __global__ __launch_bounds__(256) void k_build(const Member* M, u32 count, u32 round) {
@@ -956,7 +1058,7 @@ __device__ __forceinline__ u32 any_pending(const Member* M, u32 count, u32 round
 }
 
 __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count, u32 first,
-                                                      u32 last, u32 tail) {
+                                                      u32 last, u32 tail, u32 grouped) {
     __shared__ u32 s_any;
     // pending roots from the round before: the same for every workgroup
     // (written before the last barrier or launch, read after it)
@@ -972,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_rounds_alloc(const Member* M, u32 count
                 __syncthreads();
                 if (!s_any) break;  // uniform
             }
-            count_hist_body(M, count, round, tail);
+            count_hist_body(M, count, round, tail, grouped);
             bool ok = grid_barrier(bar, tail);
             if (ok) {
                 build_body(M, count, round, tail);
@@ -1349,7 +1451,8 @@ __device__ __forceinline__ void flush_staged(const DevTree& t, u32 stripe, u32* 
 // voxel counts are summed in LDS and flushed once per workgroup, and claimed
 // cells are staged in LDS and appended with one atomic per workgroup on one
 // of kStripes counters (workgroup id mod kStripes, i.e. one per XCD).
-__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count, u32 use_table) {
+__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count, u32 use_table,
+                                                      u32 grouped) {
     __shared__ u32 s_claims[kClaimBuf];
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
@@ -1389,7 +1492,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         const DevTree* tp = M[c].tree;
         const u32 S = tp->ctr->spill_count;
         const u32 j = (tile - s_pre[c]) * kWG + tid;
-        if (j < S + M[c].n) fetch_work(*tp, M[c].batch, S, M[c].base_key, j, rec, key);
+        if (j < S + M[c].n)
+            fetch_work(*tp, M[c].batch, grouped && tp->grp_rec, S, M[c].base_key, j, rec, key);
     };
     u32 tile = first_tile(nwg);
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
@@ -1480,7 +1584,10 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         // one round trip for the tile: claim CASes, one slot reservation per
         // leaf, and the next tile's records
         ClaimBatch cb;
-        claim_issue(t, s_ctag, s_cval, s_live, s_nlive, s_ovf, s_novf, cb, cn == c);
+        // dominance markers need keys increasing along the workgroup's tiles,
+        // which the leaf-grouped order does not keep
+        claim_issue(t, s_ctag, s_cval, s_live, s_nlive, s_ovf, s_novf, cb,
+                    cn == c && !(grouped && t.grp_rec));
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
@@ -1546,6 +1653,7 @@ __device__ __forceinline__ void pass_bookkeeping(const Member& mb) {
     c->final_count = 0u;
     c->vtouched_count = 0u;
     c->touched_count = 0u;
+    c->bucket_top = 0u;
     c->pending_count[0] = c->pending_count[1] = 0u;
     c->hist_top = 0u;
     c->build_rounds = 0u;
@@ -1812,9 +1920,18 @@ hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape
     hipLaunchKernelGGL(k_count_leaves, dim3(g), dim3(kWG), 0, s, ga);
     return hipGetLastError();
 }
+static inline u32 grouped_pass(u64 items) { return items >= kGroupMinItems ? 1u : 0u; }
+
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s) {
     hipLaunchKernelGGL(k_split_leaves, dim3(grid_for(items / 64u, 64, 1024)), dim3(kWG), 0, s, m,
-                       count);
+                       count, grouped_pass(items));
+    return hipGetLastError();
+}
+hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                              hipStream_t s) {
+    if (!grouped_pass(items)) return hipSuccess;
+    const u32 g = grid_for(items / kGroupTiles, 8, sh.cap[kShapeCount]);
+    hipLaunchKernelGGL(k_group_batch, dim3(g), dim3(kWG), 0, s, m, count);
     return hipGetLastError();
 }
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
@@ -1827,7 +1944,8 @@ hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
     const u32 cap2 = items >= (4ull << 20) ? std::max<u32>(cap, 4096u) : cap;
     const u32 g = round == 2u ? grid_for(items + 65536u, 64, cap2)
                               : grid_for(items / 4u, 32, std::max<u32>(cap / 2u, 32u));
-    hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, m, count, round);
+    hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, m, count, round,
+                       grouped_pass(items));
     return hipGetLastError();
 }
 hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
@@ -1853,10 +1971,11 @@ static u32 tail_workgroups() {
     return tail;
 }
 
-hipError_t launch_rounds_alloc(const Member* m, u32 count, u32 first, u32 last, hipStream_t s) {
+hipError_t launch_rounds_alloc(const Member* m, u32 count, u64 items, u32 first, u32 last,
+                               hipStream_t s) {
     const u32 tail = tail_workgroups();
     hipLaunchKernelGGL(k_rounds_alloc, dim3(std::max<u32>(tail, 1024u)), dim3(kWG), 0, s, m,
-                       count, first, last, tail);
+                       count, first, last, tail, grouped_pass(items));
     return hipGetLastError();
 }
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
@@ -1869,7 +1988,8 @@ hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const Laun
     // the LDS candidate table pays on large passes (a 10M-point scan's tiles
     // meet hundreds of repeated cells), not on 1M-point ones
     const u32 use_table = items >= (4ull << 20) ? 1u : 0u;
-    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count, use_table);
+    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count, use_table,
+                       grouped_pass(items));
     return hipGetLastError();
 }
 hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,

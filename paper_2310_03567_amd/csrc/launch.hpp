@@ -22,6 +22,10 @@ const void* count_leaves_kernel();  // the pass's first kernel (graph replay)
 hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s);
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s);
+// Passes of at least kGroupMinItems points: the batch copied into the
+// leaf-grouped order (nothing launched below that size).  After the split.
+hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
+                              hipStream_t s);
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
                              const LaunchShape& sh, hipStream_t s);
 hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s);
@@ -29,7 +33,8 @@ hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s);
 // chunks of the final leaves (launch_alloc with voxels = 0), in one launch.
 // The member table must have room for two barrier words after its `count`
 // entries.
-hipError_t launch_rounds_alloc(const Member* m, u32 count, u32 first, u32 last, hipStream_t s);
+hipError_t launch_rounds_alloc(const Member* m, u32 count, u64 items, u32 first, u32 last,
+                               hipStream_t s);
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s);
 hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                                hipStream_t s);

@@ -65,6 +65,15 @@ __host__ __device__ __forceinline__ u32 hist_level_offset(u32 j) {  // (8^j - 8)
     return ((1u << (3u * j)) - 8u) / 7u;
 }
 
+// Passes of at least this many batch points (summed over a group) process
+// the batch grouped by first-round leaf: the points of a leaf's region then
+// share tiles, so their voxel claims meet in one workgroup's LDS table and
+// their claim-table lines and grid words in one L2, where in scan order
+// (points of many regions interleaved) they reach global memory from many
+// workgroups.  The order does not change the octree: every result is fixed
+// by the points' keys.
+constexpr u64 kGroupMinItems = 4ull << 20;
+
 // Device-resident counters of one octree.
 struct Counters {
     u32 node_count;
@@ -77,7 +86,7 @@ struct Counters {
     u32 final_count;     // leaves finalized this pass
     u32 vtouched_count;  // inner nodes that claimed voxels this pass
     u32 touched_count;   // leaves counted in the first round
-    u32 pad0;
+    u32 bucket_top;      // batch points given a place in the leaf-grouped order
     u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
     u32 pending_count[2];       // pending roots listed by round k in [k & 1]
     u32 hist_top;        // histogram slots handed out this pass
@@ -149,6 +158,12 @@ struct DevTree {
     u32 hist_cap;
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
     GPtr<u32> item_leaf;      // per batch item: its leaf in the first round
+    // Large passes (kGroupMinItems points or more) process the batch grouped
+    // by first-round leaf; null when max_batch is below that size.
+    GPtr<uint4> grp_rec;      // batch records in the grouped order
+    GPtr<u32> grp_index;      // their indices in the batch (key = base_key + index)
+    GPtr<u32> grp_leaf;       // their first-round leaves
+    GPtr<u32> grp_next;       // per leaf: next position of its group
     u32 active_cap;
     GPtr<u64> hent;           // voxel claim table, 16-byte entries, 8 to a bucket:
                          // [2h] = claim word (tag << 32 | key), min-reduced,

@@ -38,7 +38,7 @@ OVF_NODES, OVF_ARENA, OVF_SPILL, OVF_BACKLOG, OVF_WORK, OVF_HASH = 1, 2, 4, 8, 1
 OVF_INTERNAL, OVF_HIST = 64, 128
 
 KERNEL_NAMES = ("count", "split", "alloc_points", "sample_store", "alloc_voxels",
-                "store_voxels", "finish", "count_hist", "build")
+                "store_voxels", "finish", "count_hist", "build", "group_batch")
 
 # 16-byte point record: float32 x, y, z and r, g, b, a bytes (rgba as one
 # little-endian u32: r in the low byte).
@@ -94,7 +94,8 @@ class ServerConfig(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_uint64 * 9), ("total_ms", ctypes.c_double * 9)]
+    _fields_ = [("launches", ctypes.c_uint64 * len(KERNEL_NAMES)),
+                ("total_ms", ctypes.c_double * len(KERNEL_NAMES))]
 
 
 EXPORTS = {
