@@ -6,6 +6,9 @@
 //       becomes a pending root: it is listed as a spill job (its stored
 //       points are copied to the spill buffer in the next kernel) and it gets
 //       a histogram slot (subsection "Expanding the Octree")
+//   k_group_batch        passes of 4M points or more: the batch copied into
+//                        the order grouped by first-round leaf, which the
+//                        later kernels read (same octree, better locality)
 //   k_count_hist, k_build   round 2: every point in a pending root adds to
 //       the root's histogram of its descendants kHistLevels levels down (and
 //       spilled points are copied out of their leaf's chunks); the build
