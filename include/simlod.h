@@ -213,8 +213,9 @@ typedef struct simlod_stats_data {
 #define SIMLOD_KERNEL_COUNT_HIST 7   /* expansion: split histograms         */
 #define SIMLOD_KERNEL_BUILD 8        /* expansion: multi-level subtree build
                                         (round 2)                           */
-#define SIMLOD_KERNEL_GROUP_BATCH 9  /* passes of 4M+ points: the batch
-                                        grouped by first-round leaf         */
+#define SIMLOD_KERNEL_GROUP_BATCH 9  /* passes of one octree and 4M+ points:
+                                        the batch grouped by first-round
+                                        leaf                                */
 #define SIMLOD_NUM_KERNELS 10
 typedef struct simlod_kernel_times {
     uint64_t launches[SIMLOD_NUM_KERNELS];

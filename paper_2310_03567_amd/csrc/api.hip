@@ -284,7 +284,7 @@ hipError_t enqueue_group_pass(const GroupArgs& ga, u64 items, u32 rounds, const 
                          [&] { return launch_count_leaves(ga, items, sh, s); });
     if (e == hipSuccess)
         e = timed(tm, SIMLOD_KERNEL_SPLIT, s, [&] { return launch_split_leaves(M, cnt, items, s); });
-    if (e == hipSuccess && items >= kGroupMinItems)
+    if (e == hipSuccess && cnt == 1u && items >= kGroupMinItems)
         e = timed(tm, SIMLOD_KERNEL_GROUP_BATCH, s,
                   [&] { return launch_group_batch(M, cnt, items, sh, s); });
     if (rounds >= 2u && e == hipSuccess) {

@@ -6,9 +6,10 @@
 //       becomes a pending root: it is listed as a spill job (its stored
 //       points are copied to the spill buffer in the next kernel) and it gets
 //       a histogram slot (subsection "Expanding the Octree")
-//   k_group_batch        passes of 4M points or more: the batch copied into
-//                        the order grouped by first-round leaf, which the
-//                        later kernels read (same octree, better locality)
+//   k_group_batch        passes of one octree and 4M points or more: the
+//                        batch copied into the order grouped by first-round
+//                        leaf, which the later kernels read (same octree,
+//                        better locality)
 //   k_count_hist, k_build   round 2: every point in a pending root adds to
 //       the root's histogram of its descendants kHistLevels levels down (and
 //       spilled points are copied out of their leaf's chunks); the build
@@ -1923,16 +1924,21 @@ hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape
     hipLaunchKernelGGL(k_count_leaves, dim3(g), dim3(kWG), 0, s, ga);
     return hipGetLastError();
 }
-static inline u32 grouped_pass(u64 items) { return items >= kGroupMinItems ? 1u : 0u; }
+// Passes that process the batch in leaf-grouped order: one octree, a large
+// batch.  (In group passes the members' batches are smaller, many of them
+// already in good order, and the copy cost more than it saved.)
+static inline u32 grouped_pass(u32 count, u64 items) {
+    return count == 1u && items >= kGroupMinItems ? 1u : 0u;
+}
 
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s) {
     hipLaunchKernelGGL(k_split_leaves, dim3(grid_for(items / 64u, 64, 1024)), dim3(kWG), 0, s, m,
-                       count, grouped_pass(items));
+                       count, grouped_pass(count, items));
     return hipGetLastError();
 }
 hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                               hipStream_t s) {
-    if (!grouped_pass(items)) return hipSuccess;
+    if (!grouped_pass(count, items)) return hipSuccess;
     const u32 g = grid_for(items / kGroupTiles, 8, sh.cap[kShapeCount]);
     hipLaunchKernelGGL(k_group_batch, dim3(g), dim3(kWG), 0, s, m, count);
     return hipGetLastError();
@@ -1948,7 +1954,7 @@ hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,
     const u32 g = round == 2u ? grid_for(items + 65536u, 64, cap2)
                               : grid_for(items / 4u, 32, std::max<u32>(cap / 2u, 32u));
     hipLaunchKernelGGL(k_count_hist, dim3(g), dim3(kWG), 0, s, m, count, round,
-                       grouped_pass(items));
+                       grouped_pass(count, items));
     return hipGetLastError();
 }
 hipError_t launch_build(const Member* m, u32 count, u32 round, hipStream_t s) {
@@ -1978,7 +1984,7 @@ hipError_t launch_rounds_alloc(const Member* m, u32 count, u64 items, u32 first,
                                hipStream_t s) {
     const u32 tail = tail_workgroups();
     hipLaunchKernelGGL(k_rounds_alloc, dim3(std::max<u32>(tail, 1024u)), dim3(kWG), 0, s, m,
-                       count, first, last, tail, grouped_pass(items));
+                       count, first, last, tail, grouped_pass(count, items));
     return hipGetLastError();
 }
 hipError_t launch_alloc(const Member* m, u32 count, u32 voxels, hipStream_t s) {
@@ -1992,7 +1998,7 @@ hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const Laun
     // meet hundreds of repeated cells), not on 1M-point ones
     const u32 use_table = items >= (4ull << 20) ? 1u : 0u;
     hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count, use_table,
-                       grouped_pass(items));
+                       grouped_pass(count, items));
     return hipGetLastError();
 }
 hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,

@@ -22,8 +22,9 @@ const void* count_leaves_kernel();  // the pass's first kernel (graph replay)
 hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s);
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s);
-// Passes of at least kGroupMinItems points: the batch copied into the
-// leaf-grouped order (nothing launched below that size).  After the split.
+// Passes of one octree with at least kGroupMinItems points: the batch
+// copied into the leaf-grouped order (nothing launched otherwise).  After
+// the split.
 hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                               hipStream_t s);
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,

@@ -65,8 +65,8 @@ __host__ __device__ __forceinline__ u32 hist_level_offset(u32 j) {  // (8^j - 8)
     return ((1u << (3u * j)) - 8u) / 7u;
 }
 
-// Passes of at least this many batch points (summed over a group) process
-// the batch grouped by first-round leaf: the points of a leaf's region then
+// Passes of one octree with at least this many batch points process the
+// batch grouped by first-round leaf: the points of a leaf's region then
 // share tiles, so their voxel claims meet in one workgroup's LDS table and
 // their claim-table lines and grid words in one L2, where in scan order
 // (points of many regions interleaved) they reach global memory from many
@@ -158,8 +158,9 @@ struct DevTree {
     u32 hist_cap;
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
     GPtr<u32> item_leaf;      // per batch item: its leaf in the first round
-    // Large passes (kGroupMinItems points or more) process the batch grouped
-    // by first-round leaf; null when max_batch is below that size.
+    // Large passes of one octree (kGroupMinItems points or more) process the
+    // batch grouped by first-round leaf; null when max_batch is below that
+    // size.
     GPtr<uint4> grp_rec;      // batch records in the grouped order
     GPtr<u32> grp_index;      // their indices in the batch (key = base_key + index)
     GPtr<u32> grp_leaf;       // their first-round leaves
