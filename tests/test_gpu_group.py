@@ -144,3 +144,35 @@ def test_chunk_capacity_tuner_picks_a_candidate():
     log("case: chunk tuner")
     best, ms = simlod.tune_chunk_capacity(cfg, to_device(p), [250, 1000, 4000])
     assert best in (250, 1000, 4000) and ms > 0
+
+
+def test_captured_group_of_one_takes_the_grouped_order():
+    """A group of one whose capacity is a large pass (5M points) replays,
+    from a graph, the pass that copies the batch into the leaf-grouped
+    order; passes of uneven size (one below the large-pass size) must give
+    the sequential oracle's octree."""
+    import pointgen
+    from oracle.incremental import IncrementalOracle
+    from paper_2310_03567_amd import simlod
+
+    p = pointgen.dense_scan(9_000_000, seed=27)
+    cfg = LodConfig(root_size=64.0, leaf_capacity=20_000, grid_bits=6, max_depth=12,
+                    chunk_capacity=500)
+    dev = to_device(p)
+    cuts = [0, 1_500_000, 6_000_000, 9_000_000]
+    tree = make_octree(cfg, arena_bytes=4 << 30, max_batch=5_000_000, spill_capacity=8 << 20,
+                       backlog_capacity=8 << 20, max_nodes=1 << 18)
+    log("case: captured group of one, 5M capacity, passes of 1.5M, 4.5M, 3M")
+    with simlod.Group([tree], graph=True) as g:
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            g.insert([dev[a * 16:b * 16]])
+        g.sync()
+        assert g.shape()["graph"]
+    o = IncrementalOracle(cfg)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        o.insert(p[a:b])
+    st = tree.stats()
+    assert st["status_bits"] == 0 and st["num_points"] == len(p)
+    assert_trees_equal(canonical(tree), o.canonical(), "captured group of one")
+    o.close()
+    tree.close()
