@@ -140,6 +140,37 @@ def test_large_passes_with_the_candidate_table_match_sequential_oracle():
     assert st["status_bits"] == 0 and st["num_inner"] > 1 and st["max_spilled"] > 0
 
 
+@pytest.mark.parametrize("T,r,dmax,C", [(17, 2, 6, 1), (1, 0, 3, 7), (5000, 3, 9, 1000)])
+def test_grouped_passes_of_random_clouds(T, r, dmax, C):
+    """Passes of 4.5M points take the leaf-grouped order; uniformly random
+    points (nearly every point of a window in another leaf), repeated points,
+    NaN/inf and out-of-domain points, in small-T / small-grid / C = 1
+    configurations: two passes against the sequential oracle."""
+    rng = np.random.default_rng(31 + T)
+    n = 9_000_000
+    xyz = rng.random((n, 3))
+    xyz[: n // 4] = xyz[: n // 4] ** 3  # a dense corner
+    xyz[n // 2: n // 2 + 50_000] = xyz[n // 2]  # one repeated point
+    bad = rng.integers(0, n, 64)
+    xyz[bad[:32]] = [np.nan, 0.5, 2.0]
+    xyz[bad[32:]] = [-np.inf, 1.5, 0.25]
+    p = _pts(xyz, rng.integers(0, 2**32, n, dtype=np.uint32))
+    cfg = LodConfig(leaf_capacity=T, grid_bits=r, max_depth=dmax, chunk_capacity=C)
+    dev = to_device(p)
+    o = IncrementalOracle(cfg)
+    with make_octree(cfg, arena_bytes=6 << 30, max_batch=4_500_000, spill_capacity=10 << 20,
+                     backlog_capacity=16 << 20, max_nodes=1 << 20) as tree:
+        for k in range(2):
+            log(f"case: grouped pass {k}, random cloud, T={T} r={r} Dmax={dmax} C={C}")
+            b = slice(k * 4_500_000, (k + 1) * 4_500_000)
+            tree.insert(dev[b.start * 16:b.stop * 16])
+            o.insert(p[b])
+            assert_trees_equal(canonical(tree), o.canonical(), f"after grouped pass {k}")
+        st = tree.stats()
+    o.close()
+    assert st["status_bits"] == 0 and st["num_points"] == n
+
+
 @pytest.mark.parametrize("order", ["morton", "random"])
 def test_aerial_orders_match_sequential_oracle(order):
     """The aerial height field in plain Morton order (few leaves per tile)
