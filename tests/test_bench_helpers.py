@@ -21,3 +21,13 @@ def test_algorithmic_pass_bytes_counts_each_term():
     assert bench.algorithmic_pass_bytes(0, 0, 1, 0) == 16
     assert bench.algorithmic_pass_bytes(0, 0, 0, 1) == g
     assert bench.algorithmic_pass_bytes(10, 2, 3, 1) == 360 + 80 + 48 + g
+
+
+def test_kernels_hash_covers_every_device_source():
+    import os
+
+    names = sorted(os.path.basename(f) for f in bench.KERNEL_SOURCES)
+    assert names == ["kernels.hip", "launch.hpp", "octree_device.hpp"]
+    assert all(os.path.exists(f) for f in bench.KERNEL_SOURCES)
+    h = bench.kernels_sha256()
+    assert len(h) == 64 and h == bench.kernels_sha256()
