@@ -214,8 +214,8 @@ typedef struct simlod_stats_data {
 #define SIMLOD_KERNEL_BUILD 8        /* expansion: multi-level subtree build
                                         (round 2)                           */
 #define SIMLOD_KERNEL_GROUP_BATCH 9  /* passes of one octree and 4M+ points:
-                                        the batch grouped by first-round
-                                        leaf                                */
+                                        the batch grouped by spatial
+                                        bucket                              */
 #define SIMLOD_NUM_KERNELS 10
 typedef struct simlod_kernel_times {
     uint64_t launches[SIMLOD_NUM_KERNELS];

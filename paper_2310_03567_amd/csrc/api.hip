@@ -472,7 +472,8 @@ static bool allocate_all(simlod_octree* h, const simlod_config* cfg, u64 arena_b
               dalloc(h, &t.amask[1], work) && dalloc(h, &t.item_leaf, cfg->max_batch) &&
               (cfg->max_batch < kGroupMinItems ||
                (dalloc(h, &t.grp_rec, cfg->max_batch) && dalloc(h, &t.grp_index, cfg->max_batch) &&
-                dalloc(h, &t.grp_leaf, cfg->max_batch) && dalloc(h, &t.grp_next, N))) &&
+                dalloc(h, &t.grp_leaf, cfg->max_batch) && dalloc(h, &t.bcnt, kBuckets) &&
+                dalloc(h, &t.bnext, kBuckets) && dalloc(h, &t.bsum, kBuckets / kBucketChunk))) &&
               dalloc(h, &t.hent, 2 * h->hash_entries) &&
               dalloc(h, &t.claims, cfg->backlog_capacity * kStripes) &&
               dalloc(h, &h->d_tree, 1) && dalloc(h, &h->d_members, 2);  // + pass barrier words
@@ -1172,7 +1173,7 @@ hipError_t group_capture(simlod_group* g, const GroupArgs& ga) {
         if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams p{};
         if (hipGraphKernelNodeGetParams(nd, &p) != hipSuccess) continue;
-        if (p.func == count_leaves_kernel()) {
+        if (is_count_leaves_kernel(p.func)) {
             g->head = nd;
             g->head_params = p;
         }

@@ -2,14 +2,14 @@
 // Octree").  A pass over a batch of n points runs, on one stream:
 //
 //   k_count_leaves, k_split_leaves   first expansion round: count the batch
-//       per leaf; a leaf whose stored plus new points exceed T (above Dmax)
+//       per leaf (and, on grouped passes, per spatial bucket); a leaf whose stored plus new points exceed T (above Dmax)
 //       becomes a pending root: it is listed as a spill job (its stored
 //       points are copied to the spill buffer in the next kernel) and it gets
 //       a histogram slot (subsection "Expanding the Octree")
-//   k_group_batch        passes of one octree and 4M points or more: the
-//                        batch copied into the order grouped by first-round
-//                        leaf, which the later kernels read (same octree,
-//                        better locality)
+//   k_bucket_scan, k_bucket_sums, k_group_batch   passes of one octree and
+//                        4M points or more: the batch copied into the order
+//                        grouped by spatial bucket, which the later kernels
+//                        read (same octree, better locality)
 //   k_count_hist, k_build   round 2: every point in a pending root adds to
 //       the root's histogram of its descendants kHistLevels levels down (and
 //       spilled points are copied out of their leaf's chunks); the build
@@ -70,7 +70,7 @@ __device__ __forceinline__ u32 xcd_block(u32 g) {
 }
 
 // Work item i: a spilled point (i < S) or a batch point.  grouped: the batch
-// part of the list is in the leaf-grouped order (grp_rec, grp_index).
+// part of the list is in the grouped order (grp_rec, grp_index).
 __device__ __forceinline__ void fetch_work(const DevTree& t, const uint4* batch, bool grouped,
                                            u32 S, u32 base_key, u32 i, uint4& rec, u32& key) {
     if (i < S) {
@@ -184,6 +184,7 @@ __device__ __forceinline__ u32 lds_find_or_insert(u32* keys, u32 bits, u32 key,
 
 constexpr u32 kCountProbe = 32;             // probe limit of the counting tables
 constexpr u32 kCountFlushAt = kLds / 2u;    // entries that trigger a flush
+constexpr u32 kBucketFlushAt = kLds * 3u / 4u;  // the same for the bucket table
 
 // Adds c to a leaf's first-round counter; the first addition lists the leaf.
 __device__ __forceinline__ void count_leaf_global(const DevTree& t, u32 node, u32 c) {
@@ -292,19 +293,42 @@ __device__ __forceinline__ u32* pass_barrier(const Member* M, u32 count) {
 // Reads a member of the group table into registers.
 __device__ __forceinline__ DevTree tree_of(const Member* M, u32 c) { return *M[c].tree; }
 
+// The pass processes member c's batch in the grouped order: a pass of one
+// octree with at least kGroupMinItems points, and an octree that keeps the
+// grouped buffers.  Every kernel of the pass decides alike (the launches of
+// a pass whose capacity allows it pass grouped = 1).
+__device__ __forceinline__ bool grouped_member(const Member* M, u32 count, u32 c, u32 grouped,
+                                               const DevTree& t) {
+    return grouped && count == 1u && M[c].n >= kGroupMinItems && t.grp_rec;
+}
+
+// Spatial bucket of integer position q: the Morton index of its cell at
+// kBucketBits bits per axis.
+__device__ __forceinline__ u32 bucket_of(u32 K, u32 qx, u32 qy, u32 qz) {
+    const u32 x = K >= kBucketBits ? qx >> (K - kBucketBits) : qx << (kBucketBits - K);
+    const u32 y = K >= kBucketBits ? qy >> (K - kBucketBits) : qy << (kBucketBits - K);
+    const u32 z = K >= kBucketBits ? qz >> (K - kBucketBits) : qz << (kBucketBits - K);
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
 // ---------------------------------------------------------- first round
 // Counts every batch point in its leaf.  All leaves are open in this round;
 // a leaf's total is its stored points plus this counter.  Block 0 also
 // copies the members from the kernel argument into the device table the
-// pass's later kernels read.
+// pass's later kernels read.  G: the pass may take the grouped order (then
+// the points are also counted per spatial bucket).
+template <bool G>
 __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
     __shared__ u32 lkey[kLds];
     __shared__ u32 lval[kLds];
     __shared__ u32 lfill;
+    __shared__ u32 bkey[G ? kLds : 1u], bval[G ? kLds : 1u];  // points per bucket
+    __shared__ u32 bfill;
     __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     const u32 nwg = gridDim.x;
     const u32 count = ga.count;
+    const u32 grouped = G ? 1u : 0u;
     const Member* M = ga.m;
     if (blockIdx.x == 0 && tid < count) {
         ga.table[tid] = M[tid];
@@ -313,11 +337,17 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
         for (u32 k = 0; k < kStripes; ++k) c->claim_count[k] = 0u;
     }
     if (blockIdx.x == 0 && tid < 2u) pass_barrier(ga.table, count)[tid] = 0u;
+    // the bucket table is used only by a pass that may take the grouped order
+    const bool any_grp = G && count == 1u && M[0].n >= kGroupMinItems;  // uniform
     for (u32 i = tid; i < kLds; i += kWG) {
         lkey[i] = kNone;
         lval[i] = 0u;
+        if (any_grp) {
+            bkey[i] = kNone;
+            bval[i] = 0u;
+        }
     }
-    if (tid == 0) lfill = 0u;
+    if (tid == 0) lfill = bfill = 0u;
     const u32 ntiles = member_prefix(count, s_pre, [&](u32 c) {
         return M[c].tree->ctr->status ? 0u : (M[c].n + kWG - 1u) / kWG;
     });
@@ -337,10 +367,12 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         const uint4 rec = rec_n;
         const u32 nx = next_tile(tile, ntiles, nwg);
-        u32 leaf = kNone;
+        const bool grp = G && grouped_member(M, count, c, grouped, t);
+        u32 leaf = kNone, bucket = kNone;
         if (j < n) {
             u32 qx, qy, qz;
             quantize3(t, rec, qx, qy, qz);
+            if (grp) bucket = bucket_of(t.K, qx, qy, qz);
             // directory entries first, then the next tile's record, so that
             // waiting for the entries leaves the record load in flight
             const u32 D = t.dir_depth;
@@ -363,8 +395,44 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
             else
                 count_leaf_global(t, leaf, r.len);
         }
-        count_table_tile_end(t, lkey, lval, &lfill,
-                             nx == kNone || nx >= s_pre[c + 1u]);
+        if (G && grp) {  // uniform
+            const Run rb = lane_runs(bucket);
+            if (bucket != kNone && rb.rank == 0u) {
+                const u32 e = lds_find_or_insert(bkey, kLdsBits, bucket, kCountProbe, &bfill);
+                if (e != kNone)
+                    atomicAdd(&bval[e], rb.len);
+                else
+                    atomicAdd(&t.bcnt[bucket], rb.len);
+            }
+        }
+        // both tables flush when the member ends or when one fills: the
+        // bucket table's decision shares the leaf table's barriers
+        const bool force = nx == kNone || nx >= s_pre[c + 1u];
+        __syncthreads();
+        const bool flush = force || lfill >= kCountFlushAt;
+        const bool bflush = G && grp && (force || bfill >= kBucketFlushAt);
+        __syncthreads();  // every thread has read the fills before they change
+        if (bflush) {
+            for (u32 e = tid; e < kLds; e += kWG) {
+                if (bkey[e] != kNone) {
+                    atomicAdd(&t.bcnt[bkey[e]], bval[e]);
+                    bkey[e] = kNone;
+                    bval[e] = 0u;
+                }
+            }
+            if (tid == 0) bfill = 0u;
+        }
+        if (flush) {
+            for (u32 e = tid; e < kLds; e += kWG) {
+                if (lkey[e] != kNone) {
+                    flush_count(t, lkey[e], lval[e]);
+                    lkey[e] = kNone;
+                    lval[e] = 0u;
+                }
+            }
+            if (tid == 0) lfill = 0u;
+        }
+        if (flush || bflush) __syncthreads();
         tile = nx;
     }
 }
@@ -375,10 +443,7 @@ __global__ __launch_bounds__(256) void k_count_leaves(GroupArgs ga) {
 // spill buffer (they are re-inserted with the batch) and its chunks pushed to
 // the pool (section "Chunks and the Chunk Pool").  Any other counted leaf is
 // final for the pass and listed with its number of new points.
-// grouped (uniform): the pass groups its batch by leaf; each counted leaf of
-// an octree that keeps the grouped order also gets its group's first
-// position (groups in any order).
-__global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count, u32 grouped) {
+__global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count) {
     __shared__ u32 s_dec[2];
     __shared__ i32 s_pool;
     __shared__ u32 s_pre[kMaxMembers + 1u];
@@ -396,7 +461,6 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
             const u32 cn = t.cnt[L];
             const u32 stored = t.count[L];
             const u32 depth = t.geo[L].w;
-            if (grouped && t.grp_next) t.grp_next[L] = atomicAdd(&ctr->bucket_top, cn);
             u32 pend = 0u, slot = 0u, sbase = 0u;
             if ((u64)stored + cn > (u64)t.T && depth < t.Dmax) {
                 slot = atomicAdd(&ctr->hist_top, 1u);
@@ -461,38 +525,97 @@ __global__ __launch_bounds__(256) void k_split_leaves(const Member* M, u32 count
     }
 }
 
-// ---------------------------------------------------------- leaf-grouped order
-// Large passes: the batch is copied into the order grouped by first-round
-// leaf (each leaf's group at the position the split kernel gave it; within a
-// group in the order the windows reserve their places), with each point's
-// batch index and leaf; the later kernels read the batch part of the work
-// list from there.  A workgroup takes windows of kGroupTiles tiles: it
-// counts the window's points per leaf in LDS, reserves each leaf's places
-// with one atomic (same-address atomics serialize, and every window of a
-// dense strip meets the same few leaves), then places the points.
+// ---------------------------------------------------------- grouped order
+// Large passes of one octree: the batch is copied into the order grouped by
+// spatial bucket (buckets in Morton order; within a bucket in the order the
+// windows reserve their places), with each point's batch index and
+// first-round leaf; the later kernels read the batch part of the work list
+// from there.  The first round counted the points per bucket; a scan of
+// the counts gives each bucket's first place (and clears the counts for the
+// next pass).  A workgroup then takes windows of kGroupTiles tiles: it
+// counts the window's points per bucket in LDS, reserves each bucket's
+// places with one atomic (same-address atomics serialize, and every window
+// of a dense strip meets the same few buckets), then places the points.
 constexpr u32 kGroupTiles = 8;
 constexpr u32 kGroupBits = 11;  // table entries >= the points of a window
-static_assert((1u << kGroupBits) >= kGroupTiles * 256u, "a window's leaves always fit");
+static_assert((1u << kGroupBits) >= kGroupTiles * 256u, "a window's buckets always fit");
+static_assert(kBucketChunk % kWG == 0u && kBuckets % kBucketChunk == 0u, "scan layout");
+
+__device__ u32 wg_exclusive_scan(u32* a, u32 n, u32* part);  // below
+
+// The pass takes the grouped order (its only member, a large batch, the
+// buffers, not poisoned).  One thread reads, the workgroup gets the answer:
+// uniform.
+__device__ __forceinline__ bool group_pass_on(const Member* M, u32 count) {
+    __shared__ u32 s_on;
+    if (threadIdx.x == 0) {
+        const DevTree* tp = M[0].tree;
+        s_on = count == 1u && M[0].n >= kGroupMinItems && tp->grp_rec && !tp->ctr->status;
+    }
+    __syncthreads();
+    return s_on != 0u;
+}
+
+// Exclusive scan of the bucket counts, one chunk per workgroup, into bnext
+// (chunk-relative) and bsum (chunk totals; scanned by the next kernel).
+__global__ __launch_bounds__(256) void k_bucket_scan(const Member* M, u32 count) {
+    __shared__ u32 s_wsum[kWG / 64u];
+    if (!group_pass_on(M, count)) return;  // uniform
+    const DevTree t = tree_of(M, 0u);
+    const u32 lo = blockIdx.x * kBucketChunk;
+    const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    u32 v[kBucketChunk / kWG];
+#pragma unroll
+    for (u32 k = 0; k < kBucketChunk / kWG; ++k) {  // coalesced, all in flight
+        v[k] = t.bcnt[lo + k * kWG + tid];
+        t.bcnt[lo + k * kWG + tid] = 0u;  // clear for the next pass
+    }
+    u32 carry = 0u;  // uniform: the sum of the rounds before
+#pragma unroll
+    for (u32 k = 0; k < kBucketChunk / kWG; ++k) {
+        u32 x = v[k];
+#pragma unroll
+        for (u32 o = 1; o < 64u; o <<= 1) {  // inclusive scan within the wavefront
+            const u32 y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63u) s_wsum[wave] = x;
+        __syncthreads();
+        u32 before = carry, round = 0u;
+#pragma unroll
+        for (u32 w = 0; w < kWG / 64u; ++w) {
+            if (w < wave) before += s_wsum[w];
+            round += s_wsum[w];
+        }
+        t.bnext[lo + k * kWG + tid] = before + x - v[k];
+        __syncthreads();  // s_wsum read by all before the next round writes it
+        carry += round;
+    }
+    if (tid == 0) t.bsum[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_sums(const Member* M, u32 count) {
+    __shared__ u32 s_part[4];
+    if (!group_pass_on(M, count)) return;  // uniform
+    const DevTree t = tree_of(M, 0u);
+    (void)wg_exclusive_scan(t.bsum, kBuckets / kBucketChunk, s_part);
+}
 
 __global__ __launch_bounds__(256) void k_group_batch(const Member* M, u32 count) {
     __shared__ u32 s_key[1u << kGroupBits], s_cnt[1u << kGroupBits], s_base[1u << kGroupBits];
-    __shared__ u32 s_pre[kMaxMembers + 1u];
     const u32 tid = threadIdx.x;
     for (u32 i = tid; i < (1u << kGroupBits); i += kWG) {
         s_key[i] = kNone;
         s_cnt[i] = 0u;
     }
-    const u32 nwin = member_prefix(count, s_pre, [&](u32 c) {
-        const DevTree* tp = M[c].tree;
-        const u32 per = kGroupTiles * kWG;
-        return tp->ctr->status || !tp->grp_rec ? 0u : (M[c].n + per - 1u) / per;
-    });
+    if (!group_pass_on(M, count)) return;  // uniform (its barrier orders the clearing)
+    const DevTree t = tree_of(M, 0u);
+    const u32 n = M[0].n;
+    const u32 per = kGroupTiles * kWG;
+    const u32 nwin = (n + per - 1u) / per;
     for (u32 win = xcd_block(gridDim.x); win < nwin; win += gridDim.x) {
-        const u32 c = member_of(s_pre, count, win);
-        const DevTree t = tree_of(M, c);
-        const u32 n = M[c].n;
-        const u32 j0 = (win - s_pre[c]) * (kGroupTiles * kWG) + tid;
-        u32 leaf[kGroupTiles];
+        const u32 j0 = win * per + tid;
+        u32 leaf[kGroupTiles], key[kGroupTiles];
         uint4 rec[kGroupTiles];
 #pragma unroll
         for (u32 k = 0; k < kGroupTiles; ++k) {
@@ -501,41 +624,50 @@ __global__ __launch_bounds__(256) void k_group_batch(const Member* M, u32 count)
             rec[k] = make_uint4(0u, 0u, 0u, 0u);
             if (j < n) {
                 leaf[k] = t.item_leaf[j];
-                rec[k] = M[c].batch[j];
+                rec[k] = M[0].batch[j];
             }
         }
-        // the window's points per leaf
 #pragma unroll
         for (u32 k = 0; k < kGroupTiles; ++k) {
-            const Run r = lane_runs(leaf[k]);
-            if (leaf[k] != kNone && r.rank == 0u)
-                atomicAdd(&s_cnt[lds_find_or_insert(s_key, kGroupBits, leaf[k])], r.len);
+            key[k] = kNone;
+            if (j0 + k * kWG < n) {
+                u32 qx, qy, qz;
+                quantize3(t, rec[k], qx, qy, qz);
+                key[k] = bucket_of(t.K, qx, qy, qz);
+            }
+        }
+        // the window's points per bucket
+#pragma unroll
+        for (u32 k = 0; k < kGroupTiles; ++k) {
+            const Run r = lane_runs(key[k]);
+            if (key[k] != kNone && r.rank == 0u)
+                atomicAdd(&s_cnt[lds_find_or_insert(s_key, kGroupBits, key[k])], r.len);
         }
         __syncthreads();
         for (u32 i = tid; i < (1u << kGroupBits); i += kWG) {
-            const u32 k = s_key[i];
-            if (k != kNone) s_base[i] = atomicAdd(&t.grp_next[k], s_cnt[i]);
+            const u32 b = s_key[i];
+            if (b != kNone) s_base[i] = atomicAdd(&t.bnext[b], s_cnt[i]) + t.bsum[b / kBucketChunk];
             s_cnt[i] = 0u;  // from here on: places taken within the window
         }
         __syncthreads();
 #pragma unroll
         for (u32 k = 0; k < kGroupTiles; ++k) {
             const u32 j = j0 + k * kWG;
-            const Run r = lane_runs(leaf[k]);
+            const Run r = lane_runs(key[k]);
             u32 e = kNone, r0 = 0u;
-            if (leaf[k] != kNone && r.rank == 0u) {
-                e = lds_find_or_insert(s_key, kGroupBits, leaf[k]);  // present: counted above
+            if (key[k] != kNone && r.rank == 0u) {
+                e = lds_find_or_insert(s_key, kGroupBits, key[k]);  // present: counted above
                 r0 = atomicAdd(&s_cnt[e], r.len);
             }
             e = __shfl(e, r.head);
             r0 = __shfl(r0, r.head) + r.rank;
             if (j < n) {
-                const u32 pos = leaf[k] != kNone ? s_base[e] + r0 : kNone;
+                const u32 pos = s_base[e] + r0;
                 if (pos < n) {
                     t.grp_rec[pos] = rec[k];
                     t.grp_index[pos] = j;
                     t.grp_leaf[pos] = leaf[k];
-                } else {  // the first round's counts and leaves disagree
+                } else {  // the first round's counts and these disagree
                     set_status(t, SIMLOD_OVF_INTERNAL);
                 }
             }
@@ -566,8 +698,8 @@ __device__ __forceinline__ u32 rel_index(u32 K, u32 d, u32 j, u32 qx, u32 qy, u3
 // exists (levels beyond Dmax do not); the build kernel sums the levels above
 // it from that one.  Round 2 walks all of W; later rounds only the items
 // counted in the round before.  Octrees without pending roots take no part.
-// grouped (uniform): the pass's batch is in the leaf-grouped order (octrees
-// that keep it).
+// grouped (uniform): the pass may take the grouped order (grouped_member
+// decides per member).
 __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 round, u32 nwg,
                                                 u32 grouped) {
     __shared__ u32 lkey[kLds];
@@ -595,7 +727,7 @@ __device__ __forceinline__ void count_hist_body(const Member* M, u32 count, u32 
         const uint8_t* prev = round >= 3u ? ((round & 1u) ? t.amask[0] : t.amask[1]) : nullptr;
         uint8_t* mark = (round & 1u) ? t.amask[1] : t.amask[0];
         const u32 j = (tile - s_pre[c]) * kWG + tid;
-        const bool grp = grouped && t.grp_rec;
+        const bool grp = grouped_member(M, count, c, grouped, t);
         u32 slot = kNone, depth = 0u, qx = 0u, qy = 0u, qz = 0u;
         if (j < S && !prev) {
             // round 2, a spilled item: its leaf is the spill job whose range
@@ -1455,8 +1587,9 @@ __device__ __forceinline__ void flush_staged(const DevTree& t, u32 stripe, u32* 
 // voxel counts are summed in LDS and flushed once per workgroup, and claimed
 // cells are staged in LDS and appended with one atomic per workgroup on one
 // of kStripes counters (workgroup id mod kStripes, i.e. one per XCD).
-__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count, u32 use_table,
-                                                      u32 grouped) {
+template <bool G>  // the pass may take the grouped order
+__global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count, u32 use_table) {
+    const u32 grouped = G ? 1u : 0u;
     __shared__ u32 s_claims[kClaimBuf];
     __shared__ u32 s_lkey[1u << kSlotBits], s_lcnt[1u << kSlotBits], s_lbase[1u << kSlotBits];
     __shared__ u32 s_vkey[1u << kNodeBits], s_vcnt[1u << kNodeBits];
@@ -1497,7 +1630,8 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         const u32 S = tp->ctr->spill_count;
         const u32 j = (tile - s_pre[c]) * kWG + tid;
         if (j < S + M[c].n)
-            fetch_work(*tp, M[c].batch, grouped && tp->grp_rec, S, M[c].base_key, j, rec, key);
+            fetch_work(*tp, M[c].batch, grouped_member(M, count, c, grouped, *tp), S,
+                       M[c].base_key, j, rec, key);
     };
     u32 tile = first_tile(nwg);
     uint4 rec_n = make_uint4(0u, 0u, 0u, 0u);
@@ -1589,9 +1723,9 @@ __global__ __launch_bounds__(256) void k_sample_store(const Member* M, u32 count
         // leaf, and the next tile's records
         ClaimBatch cb;
         // dominance markers need keys increasing along the workgroup's tiles,
-        // which the leaf-grouped order does not keep
+        // which the grouped order does not keep
         claim_issue(t, s_ctag, s_cval, s_live, s_nlive, s_ovf, s_novf, cb,
-                    cn == c && !(grouped && t.grp_rec));
+                    cn == c && !grouped_member(M, count, c, grouped, t));
         for (u32 i = tid; i < (1u << kSlotBits); i += kWG) {
             const u32 k = s_lkey[i];
             if (k != kNone) s_lbase[i] = atomicAdd(&t.count[k], s_lcnt[i]);
@@ -1657,7 +1791,6 @@ __device__ __forceinline__ void pass_bookkeeping(const Member& mb) {
     c->final_count = 0u;
     c->vtouched_count = 0u;
     c->touched_count = 0u;
-    c->bucket_top = 0u;
     c->pending_count[0] = c->pending_count[1] = 0u;
     c->hist_top = 0u;
     c->build_rounds = 0u;
@@ -1912,7 +2045,10 @@ static inline u32 grid_for(u64 items, u32 lo, u32 hi) {
 
 u32 expansion_rounds(u32 max_depth) { return 1u + (max_depth + kHistLevels - 1u) / kHistLevels; }
 
-const void* count_leaves_kernel() { return reinterpret_cast<const void*>(&k_count_leaves); }
+bool is_count_leaves_kernel(const void* f) {
+    return f == reinterpret_cast<const void*>(&k_count_leaves<false>) ||
+           f == reinterpret_cast<const void*>(&k_count_leaves<true>);
+}
 
 // Grid sizes depend only on `items`, the pass's batch points summed over the
 // group (or a capacity for a pass captured in a graph), and the launch shape,
@@ -1921,24 +2057,30 @@ const void* count_leaves_kernel() { return reinterpret_cast<const void*>(&k_coun
 hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s) {
     const u32 g = grid_for(items, 8, sh.cap[kShapeCount]);
-    hipLaunchKernelGGL(k_count_leaves, dim3(g), dim3(kWG), 0, s, ga);
+    if (grouped_pass(ga.count, items))
+        hipLaunchKernelGGL(k_count_leaves<true>, dim3(g), dim3(kWG), 0, s, ga);
+    else
+        hipLaunchKernelGGL(k_count_leaves<false>, dim3(g), dim3(kWG), 0, s, ga);
     return hipGetLastError();
 }
-// Passes that process the batch in leaf-grouped order: one octree, a large
-// batch.  (In group passes the members' batches are smaller, many of them
-// already in good order, and the copy cost more than it saved.)
-static inline u32 grouped_pass(u32 count, u64 items) {
+// Passes whose launches let the device take the grouped order: one octree,
+// a large batch (or capacity; each kernel checks the batch itself).  In
+// group passes the members' batches are smaller, many of them already in
+// good order, and the copy cost more than it saved.
+u32 grouped_pass(u32 count, u64 items) {
     return count == 1u && items >= kGroupMinItems ? 1u : 0u;
 }
 
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s) {
     hipLaunchKernelGGL(k_split_leaves, dim3(grid_for(items / 64u, 64, 1024)), dim3(kWG), 0, s, m,
-                       count, grouped_pass(count, items));
+                       count);
     return hipGetLastError();
 }
 hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                               hipStream_t s) {
     if (!grouped_pass(count, items)) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_scan, dim3(kBuckets / kBucketChunk), dim3(kWG), 0, s, m, count);
+    hipLaunchKernelGGL(k_bucket_sums, dim3(1), dim3(kWG), 0, s, m, count);
     const u32 g = grid_for(items / kGroupTiles, 8, sh.cap[kShapeCount]);
     hipLaunchKernelGGL(k_group_batch, dim3(g), dim3(kWG), 0, s, m, count);
     return hipGetLastError();
@@ -1997,8 +2139,10 @@ hipError_t launch_sample_store(const Member* m, u32 count, u64 items, const Laun
     // the LDS candidate table pays on large passes (a 10M-point scan's tiles
     // meet hundreds of repeated cells), not on 1M-point ones
     const u32 use_table = items >= (4ull << 20) ? 1u : 0u;
-    hipLaunchKernelGGL(k_sample_store, dim3(g), dim3(kWG), 0, s, m, count, use_table,
-                       grouped_pass(count, items));
+    if (grouped_pass(count, items))
+        hipLaunchKernelGGL(k_sample_store<true>, dim3(g), dim3(kWG), 0, s, m, count, use_table);
+    else
+        hipLaunchKernelGGL(k_sample_store<false>, dim3(g), dim3(kWG), 0, s, m, count, use_table);
     return hipGetLastError();
 }
 hipError_t launch_store_voxels(const Member* m, u32 count, u64 items, const LaunchShape& sh,
@@ -2019,6 +2163,7 @@ hipError_t launch_reset(const DevTree& t, u64 hash_entries, hipStream_t s) {
     const u64 dir_entries = dir_offset(t.dir_depth + 1u);
     const u32 gd = (u32)std::min<u64>((dir_entries + kWG - 1) / kWG, 4096);
     hipLaunchKernelGGL(k_fill_u32, dim3(gd), dim3(kWG), 0, s, t.dir, dir_entries, kNone);
+    if (t.bcnt) hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(kWG), 0, s, t.bcnt, (u64)kBuckets, 0u);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, t);
     return hipGetLastError();
 }

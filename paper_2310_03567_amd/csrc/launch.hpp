@@ -18,13 +18,17 @@ struct LaunchShape {
 inline LaunchShape default_shape() { return LaunchShape{{1024u, 1024u, 1024u, 1024u}}; }
 
 u32 expansion_rounds(u32 max_depth);
-const void* count_leaves_kernel();  // the pass's first kernel (graph replay)
+// 1 when a pass of `count` octrees over `items` points (or capacity) may take
+// the grouped order (GroupArgs.grouped of its first kernel).
+u32 grouped_pass(u32 count, u64 items);
+bool is_count_leaves_kernel(const void* f);  // the pass's first kernel (graph replay)
 hipError_t launch_count_leaves(const GroupArgs& ga, u64 items, const LaunchShape& sh,
                                hipStream_t s);
 hipError_t launch_split_leaves(const Member* m, u32 count, u64 items, hipStream_t s);
-// Passes of one octree with at least kGroupMinItems points: the batch
-// copied into the leaf-grouped order (nothing launched otherwise).  After
-// the split.
+// Passes of one octree with at least kGroupMinItems points: the first
+// round's bucket counts scanned, then the batch copied into the order
+// grouped by spatial bucket (nothing launched otherwise).  After the first
+// round.
 hipError_t launch_group_batch(const Member* m, u32 count, u64 items, const LaunchShape& sh,
                               hipStream_t s);
 hipError_t launch_count_hist(const Member* m, u32 count, u64 items, u32 round,

@@ -66,13 +66,18 @@ __host__ __device__ __forceinline__ u32 hist_level_offset(u32 j) {  // (8^j - 8)
 }
 
 // Passes of one octree with at least this many batch points process the
-// batch grouped by first-round leaf: the points of a leaf's region then
-// share tiles, so their voxel claims meet in one workgroup's LDS table and
-// their claim-table lines and grid words in one L2, where in scan order
-// (points of many regions interleaved) they reach global memory from many
-// workgroups.  The order does not change the octree: every result is fixed
-// by the points' keys.
+// batch grouped by spatial bucket (the Morton index of a point's cell at
+// kBucketBits bits per axis; buckets in Morton order, each bucket's points
+// in the order their windows reserve places): the points of a region then
+// share tiles, and neighbouring regions neighbouring tiles, so their voxel
+// claims meet in one workgroup's LDS table and their claim-table lines and
+// grid words in one L2, where in scan order (points of many regions
+// interleaved) they reach global memory from many workgroups.  The order
+// does not change the octree: every result is fixed by the points' keys.
 constexpr u64 kGroupMinItems = 4ull << 20;
+constexpr u32 kBucketBits = 8;  // per axis
+constexpr u32 kBuckets = 1u << (3u * kBucketBits);
+constexpr u32 kBucketChunk = 4096;  // buckets per scan chunk
 
 // Device-resident counters of one octree.
 struct Counters {
@@ -86,7 +91,7 @@ struct Counters {
     u32 final_count;     // leaves finalized this pass
     u32 vtouched_count;  // inner nodes that claimed voxels this pass
     u32 touched_count;   // leaves counted in the first round
-    u32 bucket_top;      // batch points given a place in the leaf-grouped order
+    u32 pad0;
     u32 claim_count[kStripes];  // voxels claimed this pass, per stripe
     u32 pending_count[2];       // pending roots listed by round k in [k & 1]
     u32 hist_top;        // histogram slots handed out this pass
@@ -159,12 +164,15 @@ struct DevTree {
     GPtr<uint8_t> amask[2];   // per work item: counted in the previous round
     GPtr<u32> item_leaf;      // per batch item: its leaf in the first round
     // Large passes of one octree (kGroupMinItems points or more) process the
-    // batch grouped by first-round leaf; null when max_batch is below that
-    // size.
+    // batch grouped by spatial bucket; null when max_batch is below that size.
     GPtr<uint4> grp_rec;      // batch records in the grouped order
     GPtr<u32> grp_index;      // their indices in the batch (key = base_key + index)
     GPtr<u32> grp_leaf;       // their first-round leaves
-    GPtr<u32> grp_next;       // per leaf: next position of its group
+    GPtr<u32> bcnt;           // per bucket: points counted in the first round
+                              // (cleared by the scan that reads them)
+    GPtr<u32> bnext;          // per bucket: next place of its group (within
+                              // its scan chunk; + bsum[chunk])
+    GPtr<u32> bsum;           // per scan chunk of buckets: first place
     u32 active_cap;
     GPtr<u64> hent;           // voxel claim table, 16-byte entries, 8 to a bucket:
                          // [2h] = claim word (tag << 32 | key), min-reduced,
